@@ -1,0 +1,203 @@
+"""Throughput of the D2Q37 thermal LBM step on one MI355X.
+
+Workload: the 2048 x 8192 Rayleigh-Taylor lattice in FP64 (16.8 M sites, 37
+populations each), seeded synthetic initial state, stepped with the fused
+path (pbc + one propagate/bc/collide kernel per step) and, beside it, the
+separate path (pbc, propagate, bc, collide).  A step is one update of the
+whole lattice.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line: MLUPS of the fused path as `value`, the roofline of
+the dominant kernel (the fused kernel: 592 algorithmic bytes per site per
+launch, HBM-bound) from HIP events recorded around every launch inside the
+timed region, the separate path's per-kernel figures, and the FP64 CPU
+oracle timed on a bounded sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "D2Q37 MLUPS, FP64 vs FP32-storage, 1 GPU; ensemble p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_SITE_FP64 = 2 * 37 * 8  # one read + one write of every population
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused_2048x8192.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1703_00185_amd", "csrc", "kernels.hip")
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    with open(KERNEL_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(lx: int, ly: int):
+    """HBM bytes per fused launch from the committed rocprofv3 counter
+    summary, or None when it is missing or the kernel source changed."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha") != kernel_source_sha() or t.get("lx") != lx or t.get("ly") != ly:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def time_path(lbm, ns, rt, path: int, steps: int, warmup: int, extra: dict):
+    import torch
+    cfg = lbm.config_from(ns, path=path, **extra)
+    lat = lbm.Lattice(cfg)
+    try:
+        lat.init_rt(rt)
+        lat.step(warmup)
+        torch.cuda.synchronize()
+        lbm.lbm_set_timing(lat.h, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms, cnt = lbm.lbm_read_timing(lat.h)
+        lbm.lbm_set_timing(lat.h, False)
+        cons = lat.conservation()
+        layout = lat.layout()
+    finally:
+        lat.close()
+    kernels = {}
+    for p, name in enumerate(lbm.PHASE_NAMES):
+        if cnt[p]:
+            kernels[name] = {"launches": int(cnt[p]), "avg_ms": float(ms[p] / cnt[p])}
+    return wall, kernels, cons, layout
+
+
+def kernel_bandwidth(kernels: dict, sites: int, lx: int, ly: int) -> dict:
+    """Algorithmic GB/s per kernel: fused/propagate/collide move 592 B per
+    site; bc reads and writes 37 values at 6 Lx sites; pbc copies 52 rows."""
+    algo = {"fused": BYTES_PER_SITE_FP64 * sites, "propagate": BYTES_PER_SITE_FP64 * sites,
+            "collide": BYTES_PER_SITE_FP64 * sites, "bc": BYTES_PER_SITE_FP64 * 6 * lx,
+            "pbc": 2 * 52 * ly * 8}
+    for name, k in kernels.items():
+        k["algorithmic_bytes"] = algo[name]
+        k["gbs"] = algo[name] / (k["avg_ms"] * 1e-3) / 1e9
+        k["hbm_frac"] = k["gbs"] / HBM_PEAK_GBS
+    return kernels
+
+
+def cpu_baseline(seconds: float):
+    """The FP64 oracle, as it stands, stepping a 2048 x 256 strip of the
+    Rayleigh-Taylor workload (same Lx and initial-state recipe, 256 rows)
+    for at least `seconds` of wall time."""
+    import oracle
+    from paper_1703_00185_amd import inputs
+    lx, ly = 2048, 256
+    ns = inputs.rt_config(lx, ly)
+    f = oracle.init_rt(lx, ly, ns, inputs.rt_perturbation(0, ly))
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        f = oracle.step(f, ns)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": lx * ly * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} FP64 oracle steps of a {lx}x{ly} Rayleigh-Taylor strip (NumPy, "
+                      f"single-threaded elementwise ops; {len(os.sched_getaffinity(0))} host cores "
+                      f"visible), {el:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--lx", type=int, default=2048)
+    ap.add_argument("--ly", type=int, default=8192)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--ny-pad", type=int, default=-1)
+    ap.add_argument("--plane-pad", type=int, default=-1)
+    ap.add_argument("--no-separate", action="store_true", help="time the fused path only")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the lattice is not sharded across GPUs)", file=sys.stderr)
+        return 2
+    if args.steps <= 0 or args.warmup < 0:
+        print("--steps must be > 0 and --warmup >= 0", file=sys.stderr)
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible: bench.py needs an MI355X", file=sys.stderr)
+        return 1
+    from paper_1703_00185_amd import inputs, lbm
+
+    lx, ly = args.lx, args.ly
+    sites = lx * ly
+    ns = inputs.rt_config(lx, ly)
+    rt = inputs.rt_perturbation(0, ly)
+    extra = {"block": args.block, "ny_pad": args.ny_pad, "plane_pad": args.plane_pad}
+
+    log(f"fused path {lx}x{ly}: {args.warmup} warmup + {args.steps} timed steps")
+    wall, kern, cons, layout = time_path(lbm, ns, rt, lbm.LBM_PATH_FUSED, args.steps, args.warmup, extra)
+    kern = kernel_bandwidth(kern, sites, lx, ly)
+    mlups = sites * args.steps / wall / 1e6
+    log(f"fused: {mlups:.1f} MLUPS, {wall / args.steps * 1e3:.3f} ms/step, "
+        f"fused kernel {kern['fused']['avg_ms']:.3f} ms = {kern['fused']['gbs']:.0f} GB/s")
+    if cons[4] != 0:
+        log(f"non-finite populations after the run: {cons[4]}")
+        return 1
+
+    separate = None
+    if not args.no_separate:
+        log(f"separate path {lx}x{ly}: {args.warmup} warmup + {args.steps} timed steps")
+        w2, k2, c2, _ = time_path(lbm, ns, rt, lbm.LBM_PATH_SEPARATE, args.steps, args.warmup, extra)
+        k2 = kernel_bandwidth(k2, sites, lx, ly)
+        separate = {"mlups": sites * args.steps / w2 / 1e6, "ms_per_step": w2 / args.steps * 1e3,
+                    "kernels": k2}
+        log(f"separate: {separate['mlups']:.1f} MLUPS")
+
+    fk = kern["fused"]
+    traffic = measured_traffic(lx, ly)
+    roofline = {"bound": "hbm", "achieved": fk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": fk["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "fused_kernel (propagate+bc+collide)",
+                "algorithmic_bytes_per_launch": fk["algorithmic_bytes"],
+                "avg_launch_ms": fk["avg_ms"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"CPU oracle baseline, about {args.cpu_seconds:.0f} s")
+        cpu = cpu_baseline(args.cpu_seconds)
+
+    out = {
+        "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"rayleigh_taylor_{lx}x{ly}_fp64", "lx": lx, "ly": ly,
+                   "path": "fused", "storage": "fp64", "layout": {
+                       "nx": layout[0], "ny_pitch": layout[1], "plane_elems": layout[2],
+                       "block": args.block or 256}},
+        "roofline": roofline, "cpu_baseline": cpu, "kernels": kern, "separate": separate,
+        "paper_equivalent_gflops": 6472 * sites * args.steps / wall / 1e9,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,197 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) D2Q37 thermal lattice Boltzmann hot path.
+ *
+ * The operations follow Calore et al., "Massively parallel Lattice Boltzmann
+ * codes on large GPU clusters" (arXiv:1703.00185):
+ *   - Sec. 2: the D2Q37 model, the discrete master equation (Eq. 6) with the
+ *     shifted equilibrium (Eqs. 4-5), the moments, and the pull form (Eq. 10);
+ *   - Sec. 2 (kernel list) and Sec. 4 (Single-GPU Implementation): per time
+ *     step, pbc (periodic-x halo columns), propagate, bc (thermal walls on
+ *     rows 0..2 and Ly-3..Ly-1) and collide, on a structure-of-arrays lattice
+ *     stored column by column (y fastest) in two copies.
+ * Where the paper is silent the library takes these readings: the 37 hops
+ * are the shells (0,0) (1,0) (1,1) (2,0) (2,1) (2,2) (3,0) (3,1) with all
+ * images; the weights solve the isotropy conditions through order 8; the
+ * equilibrium is the 4th-order Hermite projection of the Maxwellian; a
+ * population whose pull source lies beyond a wall is taken from the opposite
+ * population of the same site, and bc then resets each wall-row site to
+ * rho * K_l(T_wall) (its density times the zero-velocity equilibrium at the
+ * wall temperature).  Units: time step 1, hop e_l sites, velocity c_l = r e_l.
+ *
+ * Conventions for every call:
+ *   - Every call returns an lbm_status (0 = success) unless stated; no call
+ *     throws.  lbm_last_error() gives the reason of the last failure.
+ *   - Device memory is owned by the caller: one block of at least
+ *     lbm_required_bytes() bytes, 256-byte aligned, that must outlive the
+ *     handle.  The library never allocates or frees device memory.
+ *   - The HIP stream is owned by the caller.  Calls documented as
+ *     asynchronous only enqueue work on it; calls that take or fill host
+ *     arrays synchronise it before returning.
+ *   - Host arrays are owned by the caller.  Field arrays are [x][y] (y
+ *     fastest, Lx*Ly doubles); population arrays are [l][x][y] (37*Lx*Ly
+ *     doubles) in the population order returned by lbm_tables().
+ *   - A handle is not thread-safe: one thread, one stream per handle.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_NPOP 37
+
+typedef struct lbm_handle lbm_handle;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,  /* bad argument: NULL pointer, invalid config, n < 0 */
+  LBM_ENOMEM = -2,  /* caller's device block too small or misaligned */
+  LBM_EDEVICE = -3, /* a HIP call failed (message in lbm_last_error) */
+  LBM_ESTATE = -4   /* lattice not initialised (init_rt / set_populations) */
+} lbm_status;
+
+/* Storage type of the populations. */
+typedef enum { LBM_FP64 = 0 } lbm_storage;
+
+/* Kernel sequence of lbm_step (Sec. 2 kernel list; fusion as in Sec. 5). */
+typedef enum {
+  LBM_PATH_SEPARATE = 0, /* pbc, propagate, bc, collide: four kernels */
+  LBM_PATH_FUSED = 1     /* pbc, then one kernel doing propagate+bc+collide */
+} lbm_path;
+
+/* Single phases for lbm_run_phase and the timing counters. */
+typedef enum {
+  LBM_PHASE_PBC = 0,       /* copy the periodic-x halo columns (in place) */
+  LBM_PHASE_PROPAGATE = 1, /* pull gather into the other buffer */
+  LBM_PHASE_BC = 2,        /* thermal walls on the 6 wall rows (in place) */
+  LBM_PHASE_COLLIDE = 3,   /* collision into the other buffer */
+  LBM_PHASE_FUSED = 4,     /* propagate + bc + collide into the other buffer */
+  LBM_NPHASES = 5
+} lbm_phase;
+
+typedef struct {
+  int32_t lx, ly;    /* physical lattice, Lx >= 3 (halo of 3), Ly >= 6 */
+  double tau;        /* relaxation time, > 0.5 */
+  double gx, gy;     /* body force per unit mass (lattice units per step) */
+  double t_bottom;   /* wall temperature of rows 0..2 (> 0) */
+  double t_top;      /* wall temperature of rows Ly-3..Ly-1 (> 0) */
+  int32_t storage;   /* lbm_storage */
+  int32_t path;      /* lbm_path used by lbm_step */
+  int32_t block;     /* work-group size of the lattice kernels: 64, 128,
+                        256, 512 or 1024; 0 selects the default (256) */
+  int32_t ny_pad;    /* extra elements in the column pitch; < 0 default */
+  int64_t plane_pad; /* extra elements between population planes; < 0 default */
+} lbm_config;
+
+/* Rayleigh-Taylor initial state (the initial assignment of Sec. 2; the
+ * Rayleigh-Taylor runs of Sec. 6, Overview of Physics Results):
+ * T(x,y) = T_m - a tanh((y - y_center - h(x)) / width), with T_m and a
+ * the mean and half difference of the wall temperatures, h(x) = sum_k
+ * amp[k-1] cos(2 pi k x / Lx + phase[k-1]), k = 1..n_modes, pressure rho T in
+ * hydrostatic balance d ln p / dy = r gy / T with p = 1 on the interface,
+ * zero velocity, populations at equilibrium. */
+typedef struct {
+  double width;        /* interface width in sites, > 0 */
+  double y_center;     /* interface height in sites */
+  int32_t n_modes;     /* 0..LBM_MAX_MODES */
+  const double *amp;   /* host array of n_modes amplitudes (sites) */
+  const double *phase; /* host array of n_modes phases (radians) */
+} lbm_rt_params;
+
+#define LBM_MAX_MODES 32
+
+/* Fill *cfg with defaults for an lx x ly lattice: tau 0.8, g = (0, -1e-4),
+ * walls 1.05 (bottom) / 0.95 (top), FP64, fused path, default tiling. */
+int lbm_config_default(lbm_config *cfg, int32_t lx, int32_t ly);
+
+/* Bytes of device memory needed for cfg (two lattice copies with halos);
+ * 0 if cfg is invalid. */
+size_t lbm_required_bytes(const lbm_config *cfg);
+
+/* Bind a lattice to caller memory dev_mem (dev_bytes long) and to the HIP
+ * stream `stream` (a hipStream_t; NULL is the null stream).  *out receives
+ * the handle.  No GPU work is enqueued.  Errors: EINVAL (NULL arguments,
+ * invalid config), ENOMEM (dev_bytes too small or dev_mem not 256-byte
+ * aligned), EDEVICE (no usable device). */
+int lbm_create(const lbm_config *cfg, void *dev_mem, size_t dev_bytes,
+               void *stream, lbm_handle **out);
+
+/* Rebind the handle to another stream (asynchronous calls go there). */
+int lbm_set_stream(lbm_handle *h, void *stream);
+
+/* Set the Rayleigh-Taylor initial state (see lbm_rt_params); computed on
+ * the GPU.  Asynchronous.  Errors: EINVAL (NULL, width <= 0, n_modes out of
+ * range, non-finite amp/phase/y_center), EDEVICE. */
+int lbm_init_rt(lbm_handle *h, const lbm_rt_params *rt);
+
+/* Advance n >= 0 time steps (Eq. 6; pbc, propagate, bc, collide per step).
+ * Asynchronous.  Errors: EINVAL (n < 0), ESTATE (no state yet), EDEVICE. */
+int lbm_step(lbm_handle *h, int32_t n);
+
+/* Run one phase on the current state (test and profiling hook): PBC and BC
+ * work in place, PROPAGATE, COLLIDE and FUSED write the other copy, which
+ * then becomes current.  Asynchronous.  Errors: EINVAL, ESTATE, EDEVICE. */
+int lbm_run_phase(lbm_handle *h, int32_t phase);
+
+/* Per-site moments of the current populations (Sec. 2, under Eq. 6):
+ * rho = sum f, rho u = sum c f, 2 rho T = sum |c - u|^2 f, into host arrays
+ * of Lx*Ly doubles each ([x][y]); any of them may be NULL.  Uses the idle
+ * lattice copy as scratch.  Synchronises the stream. */
+int lbm_moments(lbm_handle *h, double *rho, double *ux, double *uy, double *T);
+
+/* Global sums of the current state: out[0] mass sum f, out[1..2] momentum
+ * sum c f, out[3] energy (1/2) sum |c|^2 f, out[4] number of populations that
+ * are NaN or infinite.  Deterministic (fixed reduction order).  Uses the
+ * idle lattice copy as scratch.  Synchronises the stream. */
+int lbm_conservation(lbm_handle *h, double out[5]);
+
+/* Copy the current populations to / from a host array [37][Lx][Ly]
+ * (checkpoint and restore; restore marks the state initialised).
+ * Synchronise the stream. */
+int lbm_get_populations(lbm_handle *h, double *host);
+int lbm_set_populations(lbm_handle *h, const double *host);
+
+/* Populations of n selected sites of the current state: out[l * n + i] =
+ * f_l(xs[i], ys[i]), host arrays, 0 <= xs[i] < Lx, 0 <= ys[i] < Ly (checked
+ * on the host: EINVAL otherwise).  n may be at most lbm_layout()[3] / 304.
+ * Uses the idle lattice copy as scratch.  Synchronises the stream. */
+int lbm_get_sites(lbm_handle *h, int32_t n, const int32_t *xs, const int32_t *ys, double *out);
+
+/* Per-phase kernel timing with HIP events recorded on the bound stream
+ * around every launch while enabled.  lbm_read_timing synchronises the
+ * stream, writes the summed milliseconds and launch counts per lbm_phase,
+ * and resets the counters. */
+int lbm_set_timing(lbm_handle *h, int32_t enable);
+int lbm_read_timing(lbm_handle *h, double ms[LBM_NPHASES], int64_t count[LBM_NPHASES]);
+
+/* Geometry of the bound lattice: out[0] columns NX = Lx + 6 (3 halo
+ * columns each side), out[1] column pitch NY (elements), out[2] population
+ * plane stride (elements), out[3] bytes of one lattice copy. */
+int lbm_layout(const lbm_handle *h, int64_t out[4]);
+
+/* Model constants as the library uses them (host only, no GPU): hops
+ * e[37][2], opposite index opp[37], weights w[37], velocity scale r.  Any
+ * pointer may be NULL. */
+int lbm_tables(int32_t *e, int32_t *opp, double *w, double *r);
+
+/* Wall factors K_l(T) = w_l [1 + th (C_l-2)/2 + th^2 (C_l^2 - 8 C_l + 8)/8],
+ * th = T - 1, C_l = r^2 |e_l|^2, as bc applies them (host only). */
+int lbm_wall_factors(double t_wall, double out[LBM_NPOP]);
+
+/* Reason of the last failure on h, or of the last failed lbm_create /
+ * lbm_required_bytes on this thread when h is NULL.  Never NULL. */
+const char *lbm_last_error(const lbm_handle *h);
+
+/* Release the host-side handle (not the caller's memory or stream).  Waits
+ * for the handle's pending work.  NULL is accepted. */
+void lbm_destroy(lbm_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

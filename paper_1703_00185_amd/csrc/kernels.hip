@@ -1,0 +1,562 @@
+// gfx950 kernels of the D2Q37 thermal lattice Boltzmann step.
+//
+// One lane per lattice site, lanes of a wavefront along y (the contiguous
+// direction of each population plane), so that each of the 37 population
+// loads and stores of a wavefront is one contiguous 512-byte segment
+// (structure-of-arrays layout, Sec. 4 "Data Structure Analysis").
+//
+// Floating point: the file is compiled without contraction; every fused
+// multiply-add below is an explicit fma().  A kernel therefore rounds
+// exactly as written, wherever the device functions are inlined: the fused
+// kernel and the separate propagate/bc/collide kernels give identical bits,
+// and bc is bit-reproducible on any IEEE-754 binary64 machine.
+#include <cmath>
+
+#include "kernels.hpp"
+
+#pragma clang fp contract(off)
+
+namespace d2q37 {
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int NXCD = 8;  // accelerator complex dies of an MI355X
+
+// Work-group ids are dealt round-robin over the 8 XCDs, each with its own
+// L2.  Renumber them so that each XCD runs one contiguous range of logical
+// tiles: neighbouring y-tiles of a column then share the 512-byte segments
+// that straddle their boundary (the +-3-row misalignment of the pull) in
+// the same L2.  Bijective for any number of groups.
+__device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
+  const int xcd = bid % NXCD;
+  const int idx = bid / NXCD;
+  const int q = nblocks / NXCD;
+  const int r = nblocks % NXCD;
+  return xcd * q + (xcd < r ? xcd : r) + idx;
+}
+
+__device__ __forceinline__ double ld(const double* base, unsigned byte_off) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+__device__ __forceinline__ void st(double* base, unsigned byte_off, double v) {
+  *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
+// acc + k * v for a small integer k known after unrolling.
+__device__ __forceinline__ double add_scaled(double acc, int k, double v) {
+  if (k == 0) return acc;
+  if (k == 1) return acc + v;
+  if (k == -1) return acc - v;
+  return fma(static_cast<double>(k), v, acc);
+}
+// k * v for a small integer k known after unrolling.
+__device__ __forceinline__ double scaled(int k, double v) {
+  if (k == 1) return v;
+  if (k == -1) return -v;
+  return static_cast<double>(k) * v;
+}
+
+// ---------------------------------------------------------------------------
+// Site-local arithmetic
+// ---------------------------------------------------------------------------
+
+// Moment sums of one site: rho = sum f, jx = sum e_x f, jy = sum e_y f,
+// eps = sum |e|^2 f (integer hops; velocities are r e).  Populations are
+// summed pairwise (l, opp(l)) and shell by shell.
+struct MomentSums {
+  double rho, jx, jy, eps;
+};
+
+__device__ __forceinline__ MomentSums moment_sums(const double (&f)[NPOP]) {
+  double shell[NSHELL];
+  double jx = 0.0, jy = 0.0;
+  shell[0] = f[0];
+#pragma unroll
+  for (int s = 1; s < NSHELL; ++s) {
+    const int lo = SHELL_START[s], hi = SHELL_START[s + 1], mid = (lo + hi) / 2;
+    double acc = 0.0;
+#pragma unroll
+    for (int l = lo; l < mid; ++l) {
+      const int m = lo + hi - 1 - l;  // opposite population: e_m = -e_l
+      const double sum = f[m] + f[l];
+      const double dif = f[m] - f[l];
+      acc = (l == lo) ? sum : acc + sum;
+      jx = add_scaled(jx, EX[m], dif);
+      jy = add_scaled(jy, EY[m], dif);
+    }
+    shell[s] = acc;
+  }
+  double rho = shell[0];
+  double eps = shell[1];
+#pragma unroll
+  for (int s = 1; s < NSHELL; ++s) rho = rho + shell[s];
+#pragma unroll
+  for (int s = 2; s < NSHELL; ++s) eps = fma(static_cast<double>(SHELL_N2[s]), shell[s], eps);
+  return {rho, jx, jy, eps};
+}
+
+// BGK collision of one site (Eqs. 4-6): moments, shifted fields
+// u + tau g and T - tau^2 |g|^2 / 2, the 4th-order Hermite equilibrium, and
+// f <- (1 - omega) f + omega f^eq.  The equilibrium of population l is
+// rho w_l P(s), s = u_shift . c_l, with per-shell coefficients
+//   P(s) = p0 + p1 s + p2 s^2 + s^3/6 + s^4/24,
+//   p0 = 1 - U/2 + U^2/8 + th (C-2)/2 + th U (4-C)/4 + th^2 (C^2-8C+8)/8,
+//   p1 = 1 - U/2 + th (C-4)/2,   p2 = 1/2 - U/4 + th (C-6)/4,
+// U = |u_shift|^2, th = T_shift - 1, C = |c_l|^2.  The even and odd parts
+// of P serve both populations of a pair (s changes sign).
+__device__ __forceinline__ void collide_site(double (&f)[NPOP], const CollideParams& p) {
+  const MomentSums m = moment_sums(f);
+  const double inv_rho = 1.0 / m.rho;
+  const double ux = R * m.jx * inv_rho;
+  const double uy = R * m.jy * inv_rho;
+  const double temp = 0.5 * (R2 * m.eps * inv_rho - (ux * ux + uy * uy));
+  const double ubx = ux + p.tgx;
+  const double uby = uy + p.tgy;
+  const double th = (temp - p.dtemp) - 1.0;
+  const double U = ubx * ubx + uby * uby;
+  const double vx = R * ubx;
+  const double vy = R * uby;
+  const double th2 = th * th;
+  // p0 = a0 + C (b0 + C d0), p1 = a1 + C b1, p2 = a2 + C b2
+  const double a0 = (((1.0 - 0.5 * U) + 0.125 * U * U) - th) + (th * U + th2);
+  const double b0 = (0.5 * th - 0.25 * th * U) - th2;
+  const double d0 = 0.125 * th2;
+  const double a1 = (1.0 - 0.5 * U) - 2.0 * th;
+  const double b1 = 0.5 * th;
+  const double a2 = (0.5 - 0.25 * U) - 1.5 * th;
+  const double b2 = 0.25 * th;
+  const double rw = m.rho * p.omega;
+  const double om1 = p.one_minus_omega;
+
+  f[0] = fma(om1, f[0], (rw * W_SHELL[0]) * a0);
+#pragma unroll
+  for (int s = 1; s < NSHELL; ++s) {
+    const double C = R2 * static_cast<double>(SHELL_N2[s]);
+    const double cs = rw * W_SHELL[s];
+    const double e0 = cs * fma(C, fma(C, d0, b0), a0);
+    const double e2 = cs * fma(C, b2, a2);
+    const double e4 = cs * (1.0 / 24.0);
+    const double o1 = cs * fma(C, b1, a1);
+    const double o3 = cs * (1.0 / 6.0);
+    const int lo = SHELL_START[s], hi = SHELL_START[s + 1], mid = (lo + hi) / 2;
+#pragma unroll
+    for (int l = lo; l < mid; ++l) {
+      const int mm = lo + hi - 1 - l;
+      double sv;
+      if (EX[mm] == 0)
+        sv = scaled(EY[mm], vy);
+      else if (EY[mm] == 0)
+        sv = scaled(EX[mm], vx);
+      else
+        sv = add_scaled(scaled(EX[mm], vx), EY[mm], vy);
+      const double ss = sv * sv;
+      const double even = fma(ss, fma(ss, e4, e2), e0);
+      const double odd = sv * fma(ss, o3, o1);
+      f[mm] = fma(om1, f[mm], even + odd);
+      f[l] = fma(om1, f[l], even - odd);
+    }
+  }
+}
+
+// bc of one wall-row site: rho = f_0 + ... + f_36 (left fold), f_l = rho K_l.
+__device__ __forceinline__ void thermalise(double (&f)[NPOP], bool bottom, const WallParams& w) {
+  double rho = f[0];
+#pragma unroll
+  for (int l = 1; l < NPOP; ++l) rho = rho + f[l];
+#pragma unroll
+  for (int l = 0; l < NPOP; ++l) f[l] = rho * (bottom ? w.kb[l] : w.kt[l]);
+}
+
+// ---------------------------------------------------------------------------
+// Lattice traversal
+// ---------------------------------------------------------------------------
+
+// Site of this lane: column x (physical), row y, first row of its wavefront.
+template <int BLOCK>
+__device__ __forceinline__ void lane_site(const Geometry& g, int& x, int& y, int& ywave) {
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  x = tile / g.ny_blocks;
+  const int yb = tile - x * g.ny_blocks;
+  y = yb * BLOCK + threadIdx.x;
+  ywave = yb * BLOCK + (threadIdx.x & ~(WAVE - 1));
+}
+
+// True (wavefront-uniform) when every row this wavefront pulls from lies
+// inside the lattice and none of its rows is a wall row.
+__device__ __forceinline__ bool interior_wave(const Geometry& g, int ywave) {
+  const int ok = (ywave >= WALL_ROWS) && (ywave + WAVE <= g.ly - WALL_ROWS);
+  return __builtin_amdgcn_readfirstlane(ok) != 0;
+}
+
+// Pull gather of Eq. (10): f_l(x, y) <- f_l(x - e_lx, y - e_ly).  Columns
+// x - e_lx < 0 or >= Lx read the halo columns filled by pbc.  Interior
+// form: the per-population offset is uniform and the per-lane byte offset
+// is shared by all 37 loads.
+__device__ __forceinline__ void gather_interior(const Geometry& g, const double* __restrict__ src,
+                                                int x, int y, double (&f)[NPOP]) {
+  const unsigned off = static_cast<unsigned>((x + HALO) * g.ny + y) * 8u;
+#pragma unroll
+  for (int l = 0; l < NPOP; ++l) {
+    const double* base = src + (static_cast<long long>(l) * g.plane - (EX[l] * g.ny + EY[l]));
+    f[l] = ld(base, off);
+  }
+}
+
+// General form, for wavefronts touching the walls: a source row beyond a
+// wall is replaced by the opposite population of the same site.
+__device__ __forceinline__ void gather_wall(const Geometry& g, const double* __restrict__ src,
+                                            int x, int y, double (&f)[NPOP]) {
+  const int X = x + HALO;
+#pragma unroll
+  for (int l = 0; l < NPOP; ++l) {
+    const int ys = y - EY[l];
+    const bool inside = (ys >= 0) && (ys < g.ly);
+    const long long idx = inside
+        ? static_cast<long long>(l) * g.plane + static_cast<long long>(X - EX[l]) * g.ny + ys
+        : static_cast<long long>(opp_of(l)) * g.plane + static_cast<long long>(X) * g.ny + y;
+    f[l] = src[idx];
+  }
+}
+
+__device__ __forceinline__ void load_site(const Geometry& g, const double* __restrict__ src,
+                                          int x, int y, double (&f)[NPOP]) {
+  const unsigned off = static_cast<unsigned>((x + HALO) * g.ny + y) * 8u;
+#pragma unroll
+  for (int l = 0; l < NPOP; ++l) f[l] = ld(src + static_cast<long long>(l) * g.plane, off);
+}
+
+__device__ __forceinline__ void store_site(const Geometry& g, double* __restrict__ dst,
+                                           int x, int y, const double (&f)[NPOP]) {
+  const unsigned off = static_cast<unsigned>((x + HALO) * g.ny + y) * 8u;
+#pragma unroll
+  for (int l = 0; l < NPOP; ++l) st(dst + static_cast<long long>(l) * g.plane, off, f[l]);
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+// Halo columns to refresh: population l with |e_lx| = k needs k columns
+// beyond each vertical boundary, 26 (population, distance) pairs per side.
+struct HaloCopies {
+  int l[52];
+  int d[52];
+  int right[52];  // 1: e_lx < 0, the copy goes to the right halo
+};
+constexpr HaloCopies make_halo_copies() {
+  HaloCopies h{};
+  int n = 0;
+  for (int l = 0; l < NPOP; ++l) {
+    const int k = EX[l] < 0 ? -EX[l] : EX[l];
+    for (int d = 1; d <= k; ++d) {
+      h.l[n] = l;
+      h.d[n] = d;
+      h.right[n] = EX[l] < 0 ? 1 : 0;
+      ++n;
+    }
+  }
+  return h;
+}
+constexpr int count_halo_copies() {
+  int n = 0;
+  for (int l = 0; l < NPOP; ++l) n += EX[l] < 0 ? -EX[l] : EX[l];
+  return n;
+}
+static_assert(count_halo_copies() == 52, "26 populations cross each vertical boundary");
+__constant__ HaloCopies kHalo = make_halo_copies();
+
+// pbc (Sec. 4): periodic x.  A population with e_x = k > 0 pulls from the
+// left halo columns X = 3 - d (d = 1..k), copies of physical column
+// Lx - d; one with e_x = -k pulls from X = Lx + 2 + d, copies of column d - 1.
+__global__ void __launch_bounds__(256) pbc_kernel(double* __restrict__ f, Geometry g) {
+  const int y = blockIdx.x * 256 + threadIdx.x;
+  if (y >= g.ly) return;
+  const int c = blockIdx.y;
+  const int l = kHalo.l[c];
+  const int d = kHalo.d[c];
+  const int dst_col = kHalo.right[c] ? g.lx + HALO - 1 + d : HALO - d;
+  const int src_col = kHalo.right[c] ? HALO - 1 + d : g.lx + HALO - d;
+  double* plane = f + static_cast<long long>(l) * g.plane;
+  plane[static_cast<long long>(dst_col) * g.ny + y] = plane[static_cast<long long>(src_col) * g.ny + y];
+}
+
+// propagate (Sec. 4): pull gather into the other lattice copy.
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK) propagate_kernel(const double* __restrict__ src,
+                                                          double* __restrict__ dst, Geometry g) {
+  int x, y, ywave;
+  lane_site<BLOCK>(g, x, y, ywave);
+  double f[NPOP];
+  if (interior_wave(g, ywave)) {
+    gather_interior(g, src, x, y, f);
+  } else {
+    gather_wall(g, src, x, y < g.ly ? y : g.ly - 1, f);
+  }
+  if (y < g.ly) store_site(g, dst, x, y, f);
+}
+
+// bc (Sec. 4): thermal walls, in place, on the 3 bottom and 3 top rows.
+__global__ void __launch_bounds__(256) bc_kernel(double* __restrict__ f, Geometry g, WallParams w) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= g.lx * 2 * WALL_ROWS) return;
+  const int x = t / (2 * WALL_ROWS);
+  const int r = t - x * (2 * WALL_ROWS);
+  const bool bottom = r < WALL_ROWS;
+  const int y = bottom ? r : g.ly - 2 * WALL_ROWS + r;
+  double v[NPOP];
+  load_site(g, f, x, y, v);
+  thermalise(v, bottom, w);
+  store_site(g, f, x, y, v);
+}
+
+// collide (Sec. 4): site-local collision into the other lattice copy.
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK) collide_kernel(const double* __restrict__ src,
+                                                        double* __restrict__ dst, Geometry g,
+                                                        CollideParams c) {
+  int x, y, ywave;
+  lane_site<BLOCK>(g, x, y, ywave);
+  if (y >= g.ly) return;
+  double f[NPOP];
+  load_site(g, src, x, y, f);
+  collide_site(f, c);
+  store_site(g, dst, x, y, f);
+}
+
+// propagate + bc + collide in registers: one read and one write of every
+// population per step (the fusion the paper applies in Sec. 5, here on
+// every row, walls included, since bc is site-local).
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK) fused_kernel(const double* __restrict__ src,
+                                                      double* __restrict__ dst, Geometry g,
+                                                      CollideParams c, WallParams w) {
+  int x, y, ywave;
+  lane_site<BLOCK>(g, x, y, ywave);
+  double f[NPOP];
+  if (interior_wave(g, ywave)) {
+    gather_interior(g, src, x, y, f);
+  } else {
+    const int yc = y < g.ly ? y : g.ly - 1;
+    gather_wall(g, src, x, yc, f);
+    if (yc < WALL_ROWS || yc >= g.ly - WALL_ROWS) thermalise(f, yc < WALL_ROWS, w);
+  }
+  collide_site(f, c);
+  if (y < g.ly) store_site(g, dst, x, y, f);
+}
+
+// Per-site rho, ux, uy, T into out[4][lx][ly] (Sec. 2 moment definitions;
+// D rho T = sum |c|^2 f - rho |u|^2).
+__global__ void __launch_bounds__(256) moments_kernel(const double* __restrict__ src,
+                                                      double* __restrict__ out, Geometry g) {
+  const long long n = static_cast<long long>(g.lx) * g.ly;
+  const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int x = static_cast<int>(i / g.ly);
+  const int y = static_cast<int>(i - static_cast<long long>(x) * g.ly);
+  double f[NPOP];
+  load_site(g, src, x, y, f);
+  const MomentSums m = moment_sums(f);
+  const double inv_rho = 1.0 / m.rho;
+  const double ux = R * m.jx * inv_rho;
+  const double uy = R * m.jy * inv_rho;
+  out[i] = m.rho;
+  out[n + i] = ux;
+  out[2 * n + i] = uy;
+  out[3 * n + i] = 0.5 * (R2 * m.eps * inv_rho - (ux * ux + uy * uy));
+}
+
+// Sum of a work-group's values in a fixed order: butterfly inside each
+// wavefront, then wavefront totals in index order.
+template <int THREADS>
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v = v + __shfl_xor(v, o, WAVE);
+  const int wave = threadIdx.x / WAVE;
+  __syncthreads();
+  if ((threadIdx.x & (WAVE - 1)) == 0) lds[wave] = v;
+  __syncthreads();
+  double s = lds[0];
+#pragma unroll
+  for (int k = 1; k < THREADS / WAVE; ++k) s = s + lds[k];
+  return s;
+}
+
+// Conservation sums, pass 1: each work-group walks a fixed strided set of
+// sites and writes its 5 partial sums.
+__global__ void __launch_bounds__(CONS_THREADS) conservation_partial_kernel(
+    const double* __restrict__ src, Geometry g, double* __restrict__ partials) {
+  __shared__ double lds[CONS_THREADS / WAVE];
+  const long long n = static_cast<long long>(g.lx) * g.ly;
+  double acc[CONS_FIELDS] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (long long i = static_cast<long long>(blockIdx.x) * CONS_THREADS + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * CONS_THREADS) {
+    const int x = static_cast<int>(i / g.ly);
+    const int y = static_cast<int>(i - static_cast<long long>(x) * g.ly);
+    double f[NPOP];
+    load_site(g, src, x, y, f);
+    int bad = 0;
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) bad += isfinite(f[l]) ? 0 : 1;
+    const MomentSums m = moment_sums(f);
+    acc[0] = acc[0] + m.rho;
+    acc[1] = acc[1] + R * m.jx;
+    acc[2] = acc[2] + R * m.jy;
+    acc[3] = acc[3] + 0.5 * (R2 * m.eps);
+    acc[4] = acc[4] + static_cast<double>(bad);
+  }
+#pragma unroll
+  for (int k = 0; k < CONS_FIELDS; ++k) {
+    const double s = block_sum<CONS_THREADS>(acc[k], lds);
+    if (threadIdx.x == 0) partials[blockIdx.x * CONS_FIELDS + k] = s;
+  }
+}
+
+// Pass 2: one work-group adds the partials in a fixed order.
+__global__ void __launch_bounds__(CONS_THREADS) conservation_final_kernel(
+    const double* __restrict__ partials, int nparts, double* __restrict__ result) {
+  __shared__ double lds[CONS_THREADS / WAVE];
+#pragma unroll
+  for (int k = 0; k < CONS_FIELDS; ++k) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += CONS_THREADS) acc = acc + partials[i * CONS_FIELDS + k];
+    const double s = block_sum<CONS_THREADS>(acc, lds);
+    if (threadIdx.x == 0) result[k] = s;
+  }
+}
+
+// Gather the populations of n listed sites (coordinates checked on the
+// host): out[l * n + i] = f_l(xy[2i], xy[2i+1]).
+__global__ void __launch_bounds__(256) get_sites_kernel(const double* __restrict__ f, Geometry g,
+                                                        const int* __restrict__ xy, int n,
+                                                        double* __restrict__ out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int x = xy[2 * i];
+  const int y = xy[2 * i + 1];
+  double v[NPOP];
+  load_site(g, f, x, y, v);
+#pragma unroll
+  for (int l = 0; l < NPOP; ++l) out[static_cast<long long>(l) * n + i] = v[l];
+}
+
+__device__ __forceinline__ double log_cosh(double z) {
+  const double a = fabs(z);
+  return (a + log1p(exp(-2.0 * a))) - 0.6931471805599453094172321;
+}
+
+// Rayleigh-Taylor initial state: tanh temperature interface perturbed by
+// Fourier modes, pressure in hydrostatic balance d ln p / dy = r gy / T
+// (closed-form integral from the interface, where p = 1), rho = p / T,
+// populations at the zero-velocity equilibrium rho K_l(T).
+__global__ void __launch_bounds__(256) init_rt_kernel(double* __restrict__ f, Geometry g, RtParams p) {
+  const long long n = static_cast<long long>(g.lx) * g.ly;
+  const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int x = static_cast<int>(i / g.ly);
+  const int y = static_cast<int>(i - static_cast<long long>(x) * g.ly);
+  const double two_pi = 6.283185307179586476925287;
+  double h = 0.0;
+  for (int k = 0; k < p.n_modes; ++k)
+    h = h + p.amp[k] * cos(two_pi * static_cast<double>(k + 1) * static_cast<double>(x) /
+                               static_cast<double>(g.lx) + p.phase[k]);
+  const double z = ((static_cast<double>(y) - p.y_center) - h) / p.width;
+  const double temp = p.tm - p.a * tanh(z);
+  const double z0 = atanh(p.a / p.tm);
+  const double integral = p.width * (p.tm * z + p.a * (log_cosh(z - z0) - log_cosh(-z0))) /
+                          (p.tm * p.tm - p.a * p.a);
+  const double rho = exp(R * p.gy * integral) / temp;
+  const double th = temp - 1.0;
+  const unsigned off = static_cast<unsigned>((x + HALO) * g.ny + y) * 8u;
+#pragma unroll
+  for (int l = 0; l < NPOP; ++l) {
+    const double C = R2 * static_cast<double>(EX[l] * EX[l] + EY[l] * EY[l]);
+    const double k = weight_of(l) * ((1.0 + th * (C - 2.0) / 2.0) + th * th * (C * C - 8.0 * C + 8.0) / 8.0);
+    st(f + static_cast<long long>(l) * g.plane, off, rho * k);
+  }
+}
+
+}  // namespace
+
+#define D2Q37_BLOCK_SWITCH(B, CALL)                         \
+  switch (B) {                                              \
+    case 64: { constexpr int BS = 64; CALL; break; }        \
+    case 128: { constexpr int BS = 128; CALL; break; }      \
+    case 256: { constexpr int BS = 256; CALL; break; }      \
+    case 512: { constexpr int BS = 512; CALL; break; }      \
+    case 1024: { constexpr int BS = 1024; CALL; break; }    \
+    default: return hipErrorInvalidValue;                   \
+  }
+
+hipError_t launch_pbc(const Geometry& g, double* f, hipStream_t s) {
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(pbc_kernel, dim3((g.ly + 255) / 256, 52), dim3(256), 0, s, f, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_propagate(const Geometry& g, const double* src, double* dst, hipStream_t s) {
+  (void)hipGetLastError();
+  D2Q37_BLOCK_SWITCH(g.block, hipLaunchKernelGGL(propagate_kernel<BS>, dim3(g.lx * g.ny_blocks),
+                                                 dim3(BS), 0, s, src, dst, g));
+  return hipGetLastError();
+}
+
+hipError_t launch_bc(const Geometry& g, double* f, const WallParams& w, hipStream_t s) {
+  const int n = g.lx * 2 * WALL_ROWS;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(bc_kernel, dim3((n + 255) / 256), dim3(256), 0, s, f, g, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_collide(const Geometry& g, const double* src, double* dst,
+                          const CollideParams& c, hipStream_t s) {
+  (void)hipGetLastError();
+  D2Q37_BLOCK_SWITCH(g.block, hipLaunchKernelGGL(collide_kernel<BS>, dim3(g.lx * g.ny_blocks),
+                                                 dim3(BS), 0, s, src, dst, g, c));
+  return hipGetLastError();
+}
+
+hipError_t launch_fused(const Geometry& g, const double* src, double* dst,
+                        const CollideParams& c, const WallParams& w, hipStream_t s) {
+  (void)hipGetLastError();
+  D2Q37_BLOCK_SWITCH(g.block, hipLaunchKernelGGL(fused_kernel<BS>, dim3(g.lx * g.ny_blocks),
+                                                 dim3(BS), 0, s, src, dst, g, c, w));
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(const Geometry& g, const double* f, double* out, hipStream_t s) {
+  const long long n = static_cast<long long>(g.lx) * g.ly;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(moments_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s,
+                     f, out, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_conservation(const Geometry& g, const double* f, double* partials,
+                               double* result, hipStream_t s) {
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(conservation_partial_kernel, dim3(CONS_BLOCKS), dim3(CONS_THREADS), 0, s, f, g,
+                     partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(conservation_final_kernel, dim3(1), dim3(CONS_THREADS), 0, s, partials,
+                     CONS_BLOCKS, result);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_sites(const Geometry& g, const double* f, const int* xy, int n, double* out,
+                            hipStream_t s) {
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(get_sites_kernel, dim3((n + 255) / 256), dim3(256), 0, s, f, g, xy, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_rt(const Geometry& g, double* f, const RtParams& p, hipStream_t s) {
+  const long long n = static_cast<long long>(g.lx) * g.ly;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(init_rt_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s,
+                     f, g, p);
+  return hipGetLastError();
+}
+
+}  // namespace d2q37

@@ -1,0 +1,67 @@
+// Launch interface between the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "d2q37_model.hpp"
+
+namespace d2q37 {
+
+// Lattice geometry in HBM.  Populations are structure-of-arrays planes
+// f[l][X][y]: X in [0, lx + 6) counts columns including 3 halo columns on
+// each side (physical column x is X = x + 3), y in [0, ny) is the row, with
+// rows >= ly being padding that is never read.  Element (l, X, y) sits at
+// l * plane + X * ny + y.
+struct Geometry {
+  int lx, ly;
+  int ny;            // column pitch, elements
+  int block;         // work-group size of the lattice kernels
+  int ny_blocks;     // ceil(ly / block)
+  long long plane;   // population plane stride, elements
+};
+
+// Scalars of the collision (Eqs. 4-6): omega = 1/tau, the shift tau*g of
+// the velocity and tau^2 |g|^2 / 2 of the temperature.
+struct CollideParams {
+  double omega;
+  double one_minus_omega;
+  double tgx, tgy;
+  double dtemp;
+};
+
+// Wall factors K_l(T_wall) for the bottom and top walls.
+struct WallParams {
+  double kb[NPOP];
+  double kt[NPOP];
+};
+
+// Rayleigh-Taylor initial state parameters.
+constexpr int MAX_MODES = 32;
+struct RtParams {
+  double tm, a;          // mean temperature, half contrast
+  double width, y_center;
+  double gy;
+  int n_modes;
+  double amp[MAX_MODES];
+  double phase[MAX_MODES];
+};
+
+constexpr int CONS_BLOCKS = 1024;  // work-groups of the conservation pass
+constexpr int CONS_THREADS = 256;
+constexpr int CONS_FIELDS = 5;     // mass, jx, jy, energy, non-finite count
+
+hipError_t launch_pbc(const Geometry& g, double* f, hipStream_t s);
+hipError_t launch_propagate(const Geometry& g, const double* src, double* dst, hipStream_t s);
+hipError_t launch_bc(const Geometry& g, double* f, const WallParams& w, hipStream_t s);
+hipError_t launch_collide(const Geometry& g, const double* src, double* dst,
+                          const CollideParams& c, hipStream_t s);
+hipError_t launch_fused(const Geometry& g, const double* src, double* dst,
+                        const CollideParams& c, const WallParams& w, hipStream_t s);
+hipError_t launch_moments(const Geometry& g, const double* f, double* out, hipStream_t s);
+hipError_t launch_conservation(const Geometry& g, const double* f, double* partials,
+                               double* result, hipStream_t s);
+hipError_t launch_get_sites(const Geometry& g, const double* f, const int* xy, int n, double* out,
+                            hipStream_t s);
+hipError_t launch_init_rt(const Geometry& g, double* f, const RtParams& p, hipStream_t s);
+
+}  // namespace d2q37

@@ -1,0 +1,470 @@
+// C ABI of the D2Q37 library (declared in include/lbm.h): argument and
+// config validation, the lattice layout in the caller's device memory, the
+// double-buffer state machine of the time step, and kernel launches on the
+// caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lbm.h"
+
+using namespace d2q37;
+
+struct lbm_handle {
+  lbm_config cfg{};
+  Geometry geo{};
+  size_t buf_bytes = 0;
+  double* buf[2] = {nullptr, nullptr};
+  int cur = 0;  // buffer holding the current populations
+  hipStream_t stream = nullptr;
+  int device = 0;
+  bool ready = false;
+  CollideParams cp{};
+  WallParams wp{};
+  std::string err;
+  // per-launch timing
+  bool timing = false;
+  std::vector<hipEvent_t> events;
+  size_t ev_used = 0;
+  struct Rec {
+    int phase;
+    size_t ev;
+  };
+  std::vector<Rec> recs;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(lbm_handle* h, int code, const std::string& msg) {
+  if (h)
+    h->err = msg;
+  else
+    g_err = msg;
+  return code;
+}
+
+#define LBM_HIP(h, expr)                                                              \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail((h), LBM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr long long kMaxPlaneElems = (1LL << 29);  // byte offsets inside a plane fit 32 bits
+
+long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
+
+struct Layout {
+  Geometry geo;
+  size_t buf_bytes;
+};
+
+// Validate cfg and derive the layout; returns LBM_OK or LBM_EINVAL with *why.
+int make_layout(const lbm_config* c, Layout* out, std::string* why) {
+  if (!c) return *why = "config is NULL", LBM_EINVAL;
+  if (c->lx < 3) return *why = "lx must be >= 3 (three halo columns per side)", LBM_EINVAL;
+  if (c->ly < 2 * WALL_ROWS) return *why = "ly must be >= 6 (two bands of 3 wall rows)", LBM_EINVAL;
+  if (!std::isfinite(c->tau) || !(c->tau > 0.5)) return *why = "tau must be finite and > 0.5", LBM_EINVAL;
+  if (!std::isfinite(c->gx) || !std::isfinite(c->gy)) return *why = "gravity must be finite", LBM_EINVAL;
+  if (!std::isfinite(c->t_bottom) || !(c->t_bottom > 0.0) || !std::isfinite(c->t_top) ||
+      !(c->t_top > 0.0))
+    return *why = "wall temperatures must be finite and > 0", LBM_EINVAL;
+  if (c->storage != LBM_FP64) return *why = "storage: only LBM_FP64 is supported", LBM_EINVAL;
+  if (c->path != LBM_PATH_SEPARATE && c->path != LBM_PATH_FUSED)
+    return *why = "path must be LBM_PATH_SEPARATE or LBM_PATH_FUSED", LBM_EINVAL;
+  const int block = c->block == 0 ? 256 : c->block;
+  if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
+    return *why = "block must be 0, 64, 128, 256, 512 or 1024", LBM_EINVAL;
+  if (c->ny_pad > (1 << 20)) return *why = "ny_pad too large", LBM_EINVAL;
+  if (c->plane_pad > (1LL << 24)) return *why = "plane_pad too large", LBM_EINVAL;
+
+  Geometry g{};
+  g.lx = c->lx;
+  g.ly = c->ly;
+  g.block = block;
+  const long long ny = round_up(c->ly, 64) + (c->ny_pad > 0 ? c->ny_pad : 0);
+  const long long nx = static_cast<long long>(c->lx) + 2 * HALO;
+  if (nx * ny >= kMaxPlaneElems)
+    return *why = "lattice too large: (lx + 6) * pitch must stay below 2^29 sites", LBM_EINVAL;
+  g.ny = static_cast<int>(ny);
+  g.ny_blocks = (c->ly + block - 1) / block;
+  if (static_cast<long long>(c->lx) * g.ny_blocks >= (1LL << 31))
+    return *why = "too many work-groups", LBM_EINVAL;
+  g.plane = round_up(nx * ny, 64) + (c->plane_pad > 0 ? c->plane_pad : 0);
+  out->geo = g;
+  out->buf_bytes = static_cast<size_t>(round_up(static_cast<long long>(NPOP) * g.plane * 8, 256));
+  return LBM_OK;
+}
+
+// Make the handle's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1, want;
+  explicit DeviceGuard(int d) : want(d) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != want) (void)hipSetDevice(want);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0 && prev != want) (void)hipSetDevice(prev);
+  }
+};
+
+double* other(lbm_handle* h) { return h->buf[h->cur ^ 1]; }
+double* current(lbm_handle* h) { return h->buf[h->cur]; }
+
+// Launch with optional timing events around it.
+template <class F>
+int timed(lbm_handle* h, int phase, F&& launch) {
+  size_t ev = 0;
+  if (h->timing) {
+    if (h->ev_used + 2 > h->events.size()) {
+      for (int k = 0; k < 256; ++k) {
+        hipEvent_t e;
+        LBM_HIP(h, hipEventCreate(&e));
+        h->events.push_back(e);
+      }
+    }
+    ev = h->ev_used;
+    h->ev_used += 2;
+    LBM_HIP(h, hipEventRecord(h->events[ev], h->stream));
+  }
+  LBM_HIP(h, launch());
+  if (h->timing) {
+    LBM_HIP(h, hipEventRecord(h->events[ev + 1], h->stream));
+    h->recs.push_back({phase, ev});
+  }
+  return LBM_OK;
+}
+
+int run_phase(lbm_handle* h, int phase) {
+  const Geometry& g = h->geo;
+  int rc = LBM_OK;
+  switch (phase) {
+    case LBM_PHASE_PBC:
+      rc = timed(h, phase, [&] { return launch_pbc(g, current(h), h->stream); });
+      break;
+    case LBM_PHASE_PROPAGATE:
+      rc = timed(h, phase, [&] { return launch_propagate(g, current(h), other(h), h->stream); });
+      if (rc == LBM_OK) h->cur ^= 1;
+      break;
+    case LBM_PHASE_BC:
+      rc = timed(h, phase, [&] { return launch_bc(g, current(h), h->wp, h->stream); });
+      break;
+    case LBM_PHASE_COLLIDE:
+      rc = timed(h, phase, [&] { return launch_collide(g, current(h), other(h), h->cp, h->stream); });
+      if (rc == LBM_OK) h->cur ^= 1;
+      break;
+    case LBM_PHASE_FUSED:
+      rc = timed(h, phase,
+                 [&] { return launch_fused(g, current(h), other(h), h->cp, h->wp, h->stream); });
+      if (rc == LBM_OK) h->cur ^= 1;
+      break;
+    default:
+      return fail(h, LBM_EINVAL, "unknown phase");
+  }
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_config_default(lbm_config* cfg, int32_t lx, int32_t ly) {
+  if (!cfg) return fail(nullptr, LBM_EINVAL, "config is NULL");
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->lx = lx;
+  cfg->ly = ly;
+  cfg->tau = 0.8;
+  cfg->gx = 0.0;
+  cfg->gy = -1e-4;
+  cfg->t_bottom = 1.05;
+  cfg->t_top = 0.95;
+  cfg->storage = LBM_FP64;
+  cfg->path = LBM_PATH_FUSED;
+  cfg->block = 0;
+  cfg->ny_pad = -1;
+  cfg->plane_pad = -1;
+  return LBM_OK;
+}
+
+size_t lbm_required_bytes(const lbm_config* cfg) {
+  Layout L{};
+  std::string why;
+  if (make_layout(cfg, &L, &why) != LBM_OK) {
+    fail(nullptr, LBM_EINVAL, why);
+    return 0;
+  }
+  return 2 * L.buf_bytes;
+}
+
+int lbm_create(const lbm_config* cfg, void* dev_mem, size_t dev_bytes, void* stream,
+               lbm_handle** out) {
+  if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  Layout L{};
+  std::string why;
+  if (make_layout(cfg, &L, &why) != LBM_OK) return fail(nullptr, LBM_EINVAL, why);
+  if (!dev_mem) return fail(nullptr, LBM_EINVAL, "dev_mem is NULL");
+  if (reinterpret_cast<uintptr_t>(dev_mem) % 256 != 0)
+    return fail(nullptr, LBM_ENOMEM, "dev_mem must be 256-byte aligned");
+  if (dev_bytes < 2 * L.buf_bytes)
+    return fail(nullptr, LBM_ENOMEM,
+                "dev_bytes " + std::to_string(dev_bytes) + " < required " + std::to_string(2 * L.buf_bytes));
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, dev_mem);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();  // do not leave the error for the next call
+    return fail(nullptr, LBM_EINVAL, std::string("dev_mem is not device memory (") +
+                                        hipGetErrorString(e) + ")");
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+    return fail(nullptr, LBM_EINVAL, "dev_mem is not device memory");
+
+  auto* h = new lbm_handle();
+  h->cfg = *cfg;
+  h->geo = L.geo;
+  h->buf_bytes = L.buf_bytes;
+  h->buf[0] = static_cast<double*>(dev_mem);
+  h->buf[1] = reinterpret_cast<double*>(static_cast<char*>(dev_mem) + L.buf_bytes);
+  h->stream = static_cast<hipStream_t>(stream);
+  h->device = attr.device;
+  const double tau = cfg->tau;
+  h->cp.omega = 1.0 / tau;
+  h->cp.one_minus_omega = 1.0 - h->cp.omega;
+  h->cp.tgx = tau * cfg->gx;
+  h->cp.tgy = tau * cfg->gy;
+  h->cp.dtemp = tau * tau * (cfg->gx * cfg->gx + cfg->gy * cfg->gy) / 2.0;
+  for (int l = 0; l < NPOP; ++l) {
+    h->wp.kb[l] = wall_factor(l, cfg->t_bottom);
+    h->wp.kt[l] = wall_factor(l, cfg->t_top);
+  }
+  *out = h;
+  return LBM_OK;
+}
+
+int lbm_set_stream(lbm_handle* h, void* stream) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
+  h->stream = static_cast<hipStream_t>(stream);
+  return LBM_OK;
+}
+
+int lbm_init_rt(lbm_handle* h, const lbm_rt_params* rt) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
+  if (!rt) return fail(h, LBM_EINVAL, "rt params are NULL");
+  if (!std::isfinite(rt->width) || !(rt->width > 0.0)) return fail(h, LBM_EINVAL, "width must be > 0");
+  if (!std::isfinite(rt->y_center)) return fail(h, LBM_EINVAL, "y_center must be finite");
+  if (rt->n_modes < 0 || rt->n_modes > LBM_MAX_MODES)
+    return fail(h, LBM_EINVAL, "n_modes must be in [0, 32]");
+  if (rt->n_modes > 0 && (!rt->amp || !rt->phase)) return fail(h, LBM_EINVAL, "amp/phase are NULL");
+  RtParams p{};
+  p.tm = 0.5 * (h->cfg.t_bottom + h->cfg.t_top);
+  p.a = 0.5 * (h->cfg.t_bottom - h->cfg.t_top);
+  p.width = rt->width;
+  p.y_center = rt->y_center;
+  p.gy = h->cfg.gy;
+  p.n_modes = rt->n_modes;
+  for (int k = 0; k < rt->n_modes; ++k) {
+    if (!std::isfinite(rt->amp[k]) || !std::isfinite(rt->phase[k]))
+      return fail(h, LBM_EINVAL, "amp/phase must be finite");
+    p.amp[k] = rt->amp[k];
+    p.phase[k] = rt->phase[k];
+  }
+  DeviceGuard dg(h->device);
+  LBM_HIP(h, launch_init_rt(h->geo, current(h), p, h->stream));
+  h->ready = true;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_handle* h, int32_t n) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
+  if (n < 0) return fail(h, LBM_EINVAL, "n must be >= 0");
+  if (!h->ready) return fail(h, LBM_ESTATE, "lattice not initialised");
+  DeviceGuard dg(h->device);
+  for (int32_t i = 0; i < n; ++i) {
+    int rc = run_phase(h, LBM_PHASE_PBC);
+    if (rc == LBM_OK) {
+      if (h->cfg.path == LBM_PATH_FUSED) {
+        rc = run_phase(h, LBM_PHASE_FUSED);
+      } else {
+        rc = run_phase(h, LBM_PHASE_PROPAGATE);
+        if (rc == LBM_OK) rc = run_phase(h, LBM_PHASE_BC);
+        if (rc == LBM_OK) rc = run_phase(h, LBM_PHASE_COLLIDE);
+      }
+    }
+    if (rc != LBM_OK) return rc;
+  }
+  return LBM_OK;
+}
+
+int lbm_run_phase(lbm_handle* h, int32_t phase) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
+  if (phase < 0 || phase >= LBM_NPHASES) return fail(h, LBM_EINVAL, "unknown phase");
+  if (!h->ready) return fail(h, LBM_ESTATE, "lattice not initialised");
+  DeviceGuard dg(h->device);
+  return run_phase(h, phase);
+}
+
+int lbm_moments(lbm_handle* h, double* rho, double* ux, double* uy, double* T) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
+  if (!h->ready) return fail(h, LBM_ESTATE, "lattice not initialised");
+  DeviceGuard dg(h->device);
+  double* scratch = other(h);
+  LBM_HIP(h, launch_moments(h->geo, current(h), scratch, h->stream));
+  const size_t n = static_cast<size_t>(h->geo.lx) * h->geo.ly;
+  double* outs[4] = {rho, ux, uy, T};
+  for (int k = 0; k < 4; ++k)
+    if (outs[k])
+      LBM_HIP(h, hipMemcpyAsync(outs[k], scratch + k * n, n * sizeof(double), hipMemcpyDeviceToHost,
+                                h->stream));
+  LBM_HIP(h, hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_conservation(lbm_handle* h, double out[5]) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
+  if (!out) return fail(h, LBM_EINVAL, "out is NULL");
+  if (!h->ready) return fail(h, LBM_ESTATE, "lattice not initialised");
+  DeviceGuard dg(h->device);
+  double* partials = other(h);
+  double* result = partials + CONS_BLOCKS * CONS_FIELDS;
+  LBM_HIP(h, launch_conservation(h->geo, current(h), partials, result, h->stream));
+  LBM_HIP(h, hipMemcpyAsync(out, result, CONS_FIELDS * sizeof(double), hipMemcpyDeviceToHost,
+                            h->stream));
+  LBM_HIP(h, hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_get_populations(lbm_handle* h, double* host) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
+  if (!host) return fail(h, LBM_EINVAL, "host is NULL");
+  if (!h->ready) return fail(h, LBM_ESTATE, "lattice not initialised");
+  DeviceGuard dg(h->device);
+  const Geometry& g = h->geo;
+  const size_t row = static_cast<size_t>(g.ly) * sizeof(double);
+  for (int l = 0; l < NPOP; ++l) {
+    const double* src = current(h) + l * g.plane + static_cast<long long>(HALO) * g.ny;
+    LBM_HIP(h, hipMemcpy2DAsync(host + static_cast<size_t>(l) * g.lx * g.ly, row, src,
+                                static_cast<size_t>(g.ny) * sizeof(double), row, g.lx,
+                                hipMemcpyDeviceToHost, h->stream));
+  }
+  LBM_HIP(h, hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_set_populations(lbm_handle* h, const double* host) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
+  if (!host) return fail(h, LBM_EINVAL, "host is NULL");
+  DeviceGuard dg(h->device);
+  const Geometry& g = h->geo;
+  const size_t row = static_cast<size_t>(g.ly) * sizeof(double);
+  for (int l = 0; l < NPOP; ++l) {
+    double* dst = current(h) + l * g.plane + static_cast<long long>(HALO) * g.ny;
+    LBM_HIP(h, hipMemcpy2DAsync(dst, static_cast<size_t>(g.ny) * sizeof(double),
+                                host + static_cast<size_t>(l) * g.lx * g.ly, row, row, g.lx,
+                                hipMemcpyHostToDevice, h->stream));
+  }
+  LBM_HIP(h, hipStreamSynchronize(h->stream));
+  h->ready = true;
+  return LBM_OK;
+}
+
+int lbm_get_sites(lbm_handle* h, int32_t n, const int32_t* xs, const int32_t* ys, double* out) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
+  if (n < 0) return fail(h, LBM_EINVAL, "n must be >= 0");
+  if (n == 0) return LBM_OK;
+  if (!xs || !ys || !out) return fail(h, LBM_EINVAL, "xs/ys/out are NULL");
+  if (!h->ready) return fail(h, LBM_ESTATE, "lattice not initialised");
+  const size_t per_site = NPOP * sizeof(double) + 2 * sizeof(int);  // 304 bytes
+  if (static_cast<size_t>(n) > h->buf_bytes / per_site)
+    return fail(h, LBM_EINVAL, "too many sites for the scratch copy");
+  std::vector<int> xy(2 * static_cast<size_t>(n));
+  for (int32_t i = 0; i < n; ++i) {
+    if (xs[i] < 0 || xs[i] >= h->geo.lx || ys[i] < 0 || ys[i] >= h->geo.ly)
+      return fail(h, LBM_EINVAL, "site " + std::to_string(i) + " outside the lattice");
+    xy[2 * i] = xs[i];
+    xy[2 * i + 1] = ys[i];
+  }
+  DeviceGuard dg(h->device);
+  double* scratch_out = other(h);
+  int* scratch_xy = reinterpret_cast<int*>(scratch_out + static_cast<size_t>(NPOP) * n);
+  LBM_HIP(h, hipMemcpyAsync(scratch_xy, xy.data(), xy.size() * sizeof(int), hipMemcpyHostToDevice,
+                            h->stream));
+  LBM_HIP(h, launch_get_sites(h->geo, current(h), scratch_xy, n, scratch_out, h->stream));
+  LBM_HIP(h, hipMemcpyAsync(out, scratch_out, static_cast<size_t>(NPOP) * n * sizeof(double),
+                            hipMemcpyDeviceToHost, h->stream));
+  LBM_HIP(h, hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_set_timing(lbm_handle* h, int32_t enable) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
+  h->timing = enable != 0;
+  return LBM_OK;
+}
+
+int lbm_read_timing(lbm_handle* h, double ms[LBM_NPHASES], int64_t count[LBM_NPHASES]) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
+  if (!ms || !count) return fail(h, LBM_EINVAL, "ms/count are NULL");
+  DeviceGuard dg(h->device);
+  LBM_HIP(h, hipStreamSynchronize(h->stream));
+  for (int p = 0; p < LBM_NPHASES; ++p) {
+    ms[p] = 0.0;
+    count[p] = 0;
+  }
+  for (const auto& r : h->recs) {
+    float t = 0.0f;
+    LBM_HIP(h, hipEventElapsedTime(&t, h->events[r.ev], h->events[r.ev + 1]));
+    ms[r.phase] += t;
+    count[r.phase] += 1;
+  }
+  h->recs.clear();
+  h->ev_used = 0;
+  return LBM_OK;
+}
+
+int lbm_layout(const lbm_handle* h, int64_t out[4]) {
+  if (!h || !out) return fail(nullptr, LBM_EINVAL, "handle/out is NULL");
+  out[0] = h->geo.lx + 2 * HALO;
+  out[1] = h->geo.ny;
+  out[2] = h->geo.plane;
+  out[3] = static_cast<int64_t>(h->buf_bytes);
+  return LBM_OK;
+}
+
+int lbm_tables(int32_t* e, int32_t* opp, double* w, double* r) {
+  for (int l = 0; l < NPOP; ++l) {
+    if (e) {
+      e[2 * l] = EX[l];
+      e[2 * l + 1] = EY[l];
+    }
+    if (opp) opp[l] = opp_of(l);
+    if (w) w[l] = weight_of(l);
+  }
+  if (r) *r = R;
+  return LBM_OK;
+}
+
+int lbm_wall_factors(double t_wall, double out[LBM_NPOP]) {
+  if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+  for (int l = 0; l < NPOP; ++l) out[l] = wall_factor(l, t_wall);
+  return LBM_OK;
+}
+
+const char* lbm_last_error(const lbm_handle* h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+void lbm_destroy(lbm_handle* h) {
+  if (!h) return;
+  {
+    DeviceGuard dg(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+  }
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+"""The 2048 x 8192 Rayleigh-Taylor lattice, in the launch configuration the
+benchmark times (fused path, default work-group size).
+
+The oracle cannot step 16.8 M sites in a test, so it checks sampled sites
+one by one: its own initial state is built only on the columns the samples
+pull from (the rest of its array stays untouched zero pages), and
+oracle.step_sites computes the step at the samples.  Samples cover the
+halo-crossing columns, the wall rows, the first rows beyond the walls and
+random interior sites.  Properties that hold at any size back this up:
+mass conservation and bit-identity of the fused and separate paths.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import FP64_TOL, err_metric, lattice, need_gpu, note
+from paper_1703_00185_amd import inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+LX, LY = 2048, 8192
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _samples():
+    """Edge columns and 32 random columns; on each, the edge rows and 20
+    random rows (so the oracle needs only ~14% of the columns)."""
+    rng = np.random.default_rng(2024)
+    cols = [0, 1, 2, 3, 1023, LX - 4, LX - 3, LX - 2, LX - 1]
+    cols += sorted(set(rng.integers(4, LX - 4, 32).tolist()))
+    edge_y = [0, 1, 2, 3, 4, 63, 64, 4095, 4096, LY - 5, LY - 4, LY - 3, LY - 2, LY - 1]
+    xs, ys = [], []
+    for x in cols:
+        rows = edge_y + rng.integers(0, LY, 20).tolist()
+        xs += [x] * len(rows)
+        ys += rows
+    return np.array(xs, dtype=np.int64), np.array(ys, dtype=np.int64)
+
+
+def _oracle_initial_state(ns, rt, xs):
+    """Oracle initial populations on the columns within 3 of the samples."""
+    T, rho = oracle.rt_fields(LX, LY, ns, rt)
+    f0 = np.zeros((37, LX, LY))
+    cols = np.unique(((xs[:, None] + np.arange(-3, 4)[None, :]) % LX).ravel())
+    for c0 in range(0, cols.size, 64):
+        c = cols[c0:c0 + 64]
+        f0[:, c, :] = oracle.equilibrium(rho[c], np.zeros_like(T[c]), np.zeros_like(T[c]), T[c])
+    return f0
+
+
+@pytest.mark.timeout(600)
+def test_full_size_step_at_sampled_sites():
+    ns = inputs.rt_config(LX, LY)
+    rt = inputs.rt_perturbation(0, LY)
+    xs, ys = _samples()
+    note("oracle initial state on sampled columns")
+    f0 = _oracle_initial_state(ns, rt, xs)
+    ref_init = f0[:, xs, ys]
+    ref_step = oracle.step_sites(f0, ns, xs, ys)
+    with lattice(ns, path=lbm.LBM_PATH_FUSED) as lat:
+        lat.init_rt(rt)
+        init = lat.sites(xs, ys)
+        m0 = lat.conservation()
+        lat.step(1)
+        step1 = lat.sites(xs, ys)
+        lat.step(1)
+        m2 = lat.conservation()
+        fused2 = lat.sites(xs, ys)
+    e_init = err_metric(init, ref_init)
+    e_step = err_metric(step1, ref_step)
+    note(f"2048x8192: init err {e_init:.2e}, step err {e_step:.2e}, "
+         f"mass drift {abs(m2[0] - m0[0]) / m0[0]:.2e}")
+    assert e_init < 1e-14
+    assert e_step < FP64_TOL
+    assert abs(m2[0] - m0[0]) / m0[0] < 1e-13
+    assert m2[4] == 0
+
+    with lattice(ns, path=lbm.LBM_PATH_SEPARATE) as lat:
+        lat.init_rt(rt)
+        lat.step(2)
+        sep2 = lat.sites(xs, ys)
+    assert np.array_equal(sep2, fused2)

@@ -1,0 +1,274 @@
+"""Parity of the HIP path with the FP64 oracle, through the C ABI.
+
+Bars: propagate and bc bit-exact; collide, the fused step and whole
+trajectories within 1e-12 (gpu_helpers.err_metric); fused and separate
+paths bit-identical to each other.  Sizes span several work-group tiles
+with ragged tails, down to the smallest lattice the ABI accepts (3 x 6).
+Every oracle input is made by the oracle or the seeded input module.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import FP64_TOL, err_metric, lattice, need_gpu, noisy_state, note
+from paper_1703_00185_amd import inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(3, 6), (4, 7), (5, 9), (3, 13), (37, 70), (64, 128), (130, 257), (9, 1100)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+@pytest.mark.parametrize("lx,ly", [(3, 6), (37, 70), (64, 128), (130, 257)])
+def test_init_rt_matches_oracle(lx, ly):
+    ns = inputs.rt_config(lx, ly)
+    rt = inputs.rt_perturbation(lx + ly, ly)
+    with lattice(ns) as lat:
+        lat.init_rt(rt)
+        got = lat.get()
+    ref = oracle.init_rt(lx, ly, ns, rt)
+    assert err_metric(got, ref) < 1e-14
+
+
+@pytest.mark.parametrize("block", [64, 256, 1024])
+@pytest.mark.parametrize("lx,ly", SIZES)
+def test_propagate_bit_exact(lx, ly, block):
+    f = 1.0 + inputs.noise(lx * 1000 + ly, (37, lx, ly), 0.3)
+    with lattice(inputs.rt_config(lx, ly), path=lbm.LBM_PATH_SEPARATE, block=block) as lat:
+        lat.set(f)
+        lat.run_phase(lbm.LBM_PHASE_PBC)
+        lat.run_phase(lbm.LBM_PHASE_PROPAGATE)
+        got = lat.get()
+    assert np.array_equal(got, oracle.propagate(f))
+
+
+@pytest.mark.parametrize("lx,ly", SIZES)
+def test_bc_bit_exact(lx, ly):
+    ns = inputs.rt_config(lx, ly, t_bottom=1.1, t_top=0.93)
+    f = noisy_state(7, lx, ly)
+    with lattice(ns, path=lbm.LBM_PATH_SEPARATE) as lat:
+        lat.set(f)
+        lat.run_phase(lbm.LBM_PHASE_BC)
+        got = lat.get()
+    assert np.array_equal(got, oracle.bc(f, ns.t_bottom, ns.t_top))
+
+
+@pytest.mark.parametrize("tau,gy", [(0.8, -1e-4), (0.55, -3e-4), (1.9, 2e-4)])
+@pytest.mark.parametrize("lx,ly", [(5, 9), (64, 128), (130, 257)])
+def test_collide_matches_oracle(lx, ly, tau, gy):
+    ns = inputs.rt_config(lx, ly, tau=tau, gravity=-gy)
+    f = noisy_state(3, lx, ly)
+    with lattice(ns, path=lbm.LBM_PATH_SEPARATE) as lat:
+        lat.set(f)
+        lat.run_phase(lbm.LBM_PHASE_COLLIDE)
+        got = lat.get()
+    e = err_metric(got, oracle.collide(f, ns.tau, ns.gx, ns.gy))
+    note(f"collide {lx}x{ly} tau={tau} err={e:.2e}")
+    assert e < FP64_TOL
+
+
+@pytest.mark.parametrize("block", [64, 256, 1024])
+@pytest.mark.parametrize("lx,ly", SIZES)
+def test_fused_phase_matches_oracle_step(lx, ly, block):
+    ns = inputs.rt_config(lx, ly)
+    f = noisy_state(11, lx, ly)
+    with lattice(ns, block=block) as lat:
+        lat.set(f)
+        lat.run_phase(lbm.LBM_PHASE_PBC)
+        lat.run_phase(lbm.LBM_PHASE_FUSED)
+        got = lat.get()
+    assert err_metric(got, oracle.step(f, ns)) < FP64_TOL
+
+
+@pytest.mark.parametrize("path", [lbm.LBM_PATH_SEPARATE, lbm.LBM_PATH_FUSED])
+def test_trajectory_64x128_100_steps(path):
+    """The small Rayleigh-Taylor workload, every one of its 100 steps."""
+    ns = inputs.rt_config(64, 128)
+    f = oracle.init_rt(64, 128, ns, inputs.rt_perturbation(0, 128))
+    worst = 0.0
+    with lattice(ns, path=path) as lat:
+        lat.set(f)
+        for s in range(100):
+            lat.step(1)
+            f = oracle.step(f, ns)
+            worst = max(worst, err_metric(lat.get(), f))
+    note(f"trajectory path={path} worst err over 100 steps {worst:.2e}")
+    assert worst < FP64_TOL
+
+
+@pytest.mark.parametrize("lx,ly", [(3, 6), (5, 13), (67, 131), (130, 257)])
+def test_short_runs_on_ragged_lattices(lx, ly):
+    ns = inputs.rt_config(lx, ly)
+    f0 = oracle.init_rt(lx, ly, ns, inputs.rt_perturbation(5, ly))
+    ref = oracle.run(f0, ns, 5)
+    for path in (lbm.LBM_PATH_SEPARATE, lbm.LBM_PATH_FUSED):
+        with lattice(ns, path=path) as lat:
+            lat.set(f0)
+            lat.step(5)
+            assert err_metric(lat.get(), ref) < FP64_TOL
+
+
+@pytest.mark.parametrize("lx,ly", [(64, 128), (130, 257)])
+def test_fused_and_separate_paths_bit_identical(lx, ly):
+    ns = inputs.rt_config(lx, ly)
+    out = []
+    for path in (lbm.LBM_PATH_SEPARATE, lbm.LBM_PATH_FUSED):
+        with lattice(ns, path=path) as lat:
+            lat.init_rt(inputs.rt_perturbation(1, ly))
+            lat.step(20)
+            out.append(lat.get())
+    assert np.array_equal(out[0], out[1])
+
+
+def test_moments_match_oracle():
+    ns = inputs.rt_config(37, 70)
+    f = noisy_state(2, 37, 70)
+    with lattice(ns) as lat:
+        lat.set(f)
+        rho, ux, uy, T = lat.moments()
+    r2, ux2, uy2, T2 = oracle.moments(f)
+    assert np.max(np.abs(rho - r2) / r2) < 1e-14
+    assert np.max(np.abs(ux - ux2)) < 1e-14
+    assert np.max(np.abs(uy - uy2)) < 1e-14
+    assert np.max(np.abs(T - T2)) < 1e-13
+
+
+def test_conservation_matches_oracle_and_is_deterministic():
+    ns = inputs.rt_config(130, 257)
+    f = noisy_state(4, 130, 257)
+    with lattice(ns) as lat:
+        lat.set(f)
+        a = lat.conservation()
+        b = lat.conservation()
+    assert np.array_equal(a, b)
+    ref = oracle.totals(f)
+    for got, want in zip(a[:4], ref):
+        assert abs(got - want) <= 1e-12 * max(1.0, abs(ref[0]))
+    assert a[4] == 0
+
+
+def test_nonfinite_populations_are_counted():
+    ns = inputs.rt_config(16, 32)
+    f = noisy_state(8, 16, 32)
+    f[5, 3, 7] = np.nan
+    f[30, 15, 31] = np.inf
+    f[0, 0, 0] = -np.inf
+    with lattice(ns) as lat:
+        lat.set(f)
+        assert lat.conservation()[4] == 3
+
+
+def test_mass_conserved_over_200_steps():
+    ns = inputs.rt_config(64, 128)
+    with lattice(ns) as lat:
+        lat.init_rt(inputs.rt_perturbation(9, 128))
+        m0 = lat.conservation()[0]
+        lat.step(200)
+        m1 = lat.conservation()[0]
+    drift = abs(m1 - m0) / m0
+    note(f"mass drift over 200 steps {drift:.2e}")
+    assert drift < 1e-13 * np.sqrt(200)
+
+
+def test_x_invariant_state_stays_x_invariant():
+    ns = inputs.rt_config(24, 96)
+    with lattice(ns) as lat:
+        lat.init_rt(inputs.flat_interface(96))
+        lat.step(30)
+        f = lat.get()
+    assert all(np.array_equal(f[:, 0, :], f[:, x, :]) for x in range(24))
+
+
+def test_uniform_rest_state_stays_uniform():
+    ns = inputs.rt_config(16, 40, gravity=0.0, t_bottom=1.0, t_top=1.0)
+    f0 = oracle.equilibrium(np.full((16, 40), 1.2), np.zeros((16, 40)), np.zeros((16, 40)),
+                            np.ones((16, 40)))
+    with lattice(ns) as lat:
+        lat.set(f0)
+        lat.step(25)
+        f = lat.get()
+    assert err_metric(f, f0) < 1e-14
+
+
+def test_determinism_and_checkpoint_resume():
+    ns = inputs.rt_config(64, 128)
+    rt = inputs.rt_perturbation(6, 128)
+    with lattice(ns) as lat:
+        lat.init_rt(rt)
+        lat.step(10)
+        ckpt = lat.get()
+        lat.step(10)
+        straight = lat.get()
+    with lattice(ns) as lat:
+        lat.set(ckpt)
+        lat.step(10)
+        resumed = lat.get()
+    with lattice(ns) as lat:
+        lat.init_rt(rt)
+        lat.step(20)
+        again = lat.get()
+    assert np.array_equal(straight, resumed)
+    assert np.array_equal(straight, again)
+
+
+def test_get_sites_matches_full_copy():
+    ns = inputs.rt_config(37, 70)
+    f = noisy_state(12, 37, 70)
+    xs = np.array([0, 36, 5, 17, 36, 0])
+    ys = np.array([0, 69, 33, 2, 0, 69])
+    with lattice(ns) as lat:
+        lat.set(f)
+        got = lat.sites(xs, ys)
+        with pytest.raises(lbm.LbmError):
+            lat.sites(np.array([37]), np.array([0]))
+        with pytest.raises(lbm.LbmError):
+            lat.sites(np.array([0]), np.array([-1]))
+    assert np.array_equal(got, f[:, xs, ys])
+
+
+def test_timing_counters_and_state_errors():
+    ns = inputs.rt_config(64, 128)
+    with lattice(ns) as lat:
+        with pytest.raises(lbm.LbmError) as ei:
+            lat.step(1)
+        assert ei.value.status == lbm.LBM_ESTATE
+        lat.init_rt(inputs.rt_perturbation(0, 128))
+        with pytest.raises(lbm.LbmError) as ei:
+            lat.step(-1)
+        assert ei.value.status == lbm.LBM_EINVAL
+        lbm.lbm_set_timing(lat.h, True)
+        lat.step(3)
+        ms, cnt = lbm.lbm_read_timing(lat.h)
+        lbm.lbm_set_timing(lat.h, False)
+    assert cnt.tolist() == [3, 0, 0, 0, 3]
+    assert ms[0] > 0 and ms[4] > 0
+
+
+def test_runs_on_a_side_stream():
+    import torch
+    ns = inputs.rt_config(64, 128)
+    f0 = oracle.init_rt(64, 128, ns, inputs.rt_perturbation(2, 128))
+    side = torch.cuda.Stream()
+    cfg = lbm.config_from(ns)
+    lat = lbm.Lattice(cfg, stream=side)
+    try:
+        lat.set(f0)
+        lat.step(3)
+        got = lat.get()
+    finally:
+        lat.close()
+    assert err_metric(got, oracle.run(f0, ns, 3)) < FP64_TOL
+
+
+def test_host_memory_pointer_rejected():
+    cfg = lbm.lbm_config_default(16, 32)
+    need = lbm.lbm_required_bytes(cfg)
+    host = np.zeros(need // 8 + 64)
+    addr = (host.ctypes.data + 255) // 256 * 256
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.lbm_create(cfg, addr, need, 0)
+    assert ei.value.status in (lbm.LBM_EINVAL, lbm.LBM_EDEVICE)
