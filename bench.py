@@ -81,6 +81,29 @@ def time_path(lbm, ns, rt, path: int, steps: int, warmup: int, extra: dict):
     return wall, kernels, cons, layout
 
 
+def copy_bandwidth(gib: float, reps: int = 10) -> dict:
+    """A plain device-to-device copy of known size (torch's copy kernel):
+    the attainable-bandwidth reference, and the calibration of the HBM
+    byte counters (it reads and writes exactly `gib` GiB per launch)."""
+    import torch
+    n = int(gib * (1 << 30))
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_per_launch": 2 * n, "avg_ms": ms, "gbs": 2 * n / (ms * 1e-3) / 1e9}
+
+
 def kernel_bandwidth(kernels: dict, sites: int, lx: int, ly: int) -> dict:
     """Algorithmic GB/s per kernel: fused/propagate/collide move 592 B per
     site; bc reads and writes 37 values at 6 Lx sites; pbc copies 52 rows."""
@@ -130,6 +153,8 @@ def main() -> int:
     ap.add_argument("--no-separate", action="store_true", help="time the fused path only")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-gib", type=float, default=2.0,
+                    help="size of the plain-copy reference (read GiB = write GiB)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -152,6 +177,9 @@ def main() -> int:
     rt = inputs.rt_perturbation(0, ly)
     extra = {"block": args.block, "ny_pad": args.ny_pad, "plane_pad": args.plane_pad}
 
+    copy = copy_bandwidth(args.copy_gib) if args.copy_gib > 0 else None
+    if copy:
+        log(f"plain copy of {args.copy_gib} GiB: {copy['gbs']:.0f} GB/s")
     log(f"fused path {lx}x{ly}: {args.warmup} warmup + {args.steps} timed steps")
     wall, kern, cons, layout = time_path(lbm, ns, rt, lbm.LBM_PATH_FUSED, args.steps, args.warmup, extra)
     kern = kernel_bandwidth(kern, sites, lx, ly)
@@ -193,6 +221,7 @@ def main() -> int:
                        "nx": layout[0], "ny_pitch": layout[1], "plane_elems": layout[2],
                        "block": args.block or 256}},
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kern, "separate": separate,
+        "copy_reference": copy,
         "paper_equivalent_gflops": 6472 * sites * args.steps / wall / 1e9,
     }
     print(json.dumps(out), flush=True)
