@@ -81,35 +81,48 @@ def time_path(lbm, ns, rt, path: int, steps: int, warmup: int, extra: dict):
     return wall, kernels, cons, layout
 
 
-def copy_bandwidth(gib: float, reps: int = 10) -> dict:
-    """A plain device-to-device copy of known size (torch's copy kernel):
-    the attainable-bandwidth reference, and the calibration of the HBM
-    byte counters (it reads and writes exactly `gib` GiB per launch)."""
+def probe_bandwidth(lbm, gib: float, reps: int = 10) -> dict:
+    """Attainable-bandwidth reference: the library's copy probes on two
+    buffers of `gib` GiB (the copy micro-benchmark of the paper's Sec. 4).
+    COPY moves 2 x bytes per launch; MRAW/ARMW (doubles, shifted by
+    -3..3 elements as the pull is) move 2 x (bytes - 1024).  The COPY
+    launch is also the known-size kernel that calibrates the HBM byte
+    counters."""
     import torch
-    n = int(gib * (1 << 30))
+    n = int(gib * (1 << 30)) // 16 * 16
     src = torch.empty(n, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
     src.fill_(1)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / reps
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def timed(mode, shift):
+        lbm.lbm_probe_bandwidth(mode, src.data_ptr(), dst.data_ptr(), n, shift, stream)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            lbm.lbm_probe_bandwidth(mode, src.data_ptr(), dst.data_ptr(), n, shift, stream)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        moved = 2 * n if mode == lbm.LBM_PROBE_COPY else 2 * (n - 1024)
+        return {"bytes_per_launch": moved, "avg_ms": ms, "gbs": moved / (ms * 1e-3) / 1e9}
+
+    out = {"copy": timed(lbm.LBM_PROBE_COPY, 0)}
+    for name, mode in (("mraw", lbm.LBM_PROBE_MRAW), ("armw", lbm.LBM_PROBE_ARMW)):
+        out[name] = {str(sh): timed(mode, sh)["gbs"] for sh in (-3, -1, 0, 1, 3)}
     del src, dst
     torch.cuda.empty_cache()
-    return {"bytes_per_launch": 2 * n, "avg_ms": ms, "gbs": 2 * n / (ms * 1e-3) / 1e9}
+    return out
 
 
-def kernel_bandwidth(kernels: dict, sites: int, lx: int, ly: int) -> dict:
-    """Algorithmic GB/s per kernel: fused/propagate/collide move 592 B per
-    site; bc reads and writes 37 values at 6 Lx sites; pbc copies 52 rows."""
-    algo = {"fused": BYTES_PER_SITE_FP64 * sites, "propagate": BYTES_PER_SITE_FP64 * sites,
-            "collide": BYTES_PER_SITE_FP64 * sites, "bc": BYTES_PER_SITE_FP64 * 6 * lx,
-            "pbc": 2 * 52 * ly * 8}
+def kernel_bandwidth(kernels: dict, sites: int, lx: int, ly: int, elem_bytes: int = 8) -> dict:
+    """Algorithmic GB/s per kernel: fused/propagate/collide read and write
+    every population once (592 B per site in FP64, 296 B in FP32); bc reads
+    and writes 37 values at 6 Lx sites; pbc copies 52 rows of Ly values."""
+    per_site = 2 * 37 * elem_bytes
+    algo = {"fused": per_site * sites, "propagate": per_site * sites,
+            "collide": per_site * sites, "bc": per_site * 6 * lx,
+            "pbc": 2 * 52 * ly * elem_bytes}
     for name, k in kernels.items():
         k["algorithmic_bytes"] = algo[name]
         k["gbs"] = algo[name] / (k["avg_ms"] * 1e-3) / 1e9
@@ -177,9 +190,10 @@ def main() -> int:
     rt = inputs.rt_perturbation(0, ly)
     extra = {"block": args.block, "ny_pad": args.ny_pad, "plane_pad": args.plane_pad}
 
-    copy = copy_bandwidth(args.copy_gib) if args.copy_gib > 0 else None
+    copy = probe_bandwidth(lbm, args.copy_gib) if args.copy_gib > 0 else None
     if copy:
-        log(f"plain copy of {args.copy_gib} GiB: {copy['gbs']:.0f} GB/s")
+        log(f"copy probe of {args.copy_gib} GiB: {copy['copy']['gbs']:.0f} GB/s; "
+            f"mraw(+1) {copy['mraw']['1']:.0f}, armw(+1) {copy['armw']['1']:.0f} GB/s")
     log(f"fused path {lx}x{ly}: {args.warmup} warmup + {args.steps} timed steps")
     wall, kern, cons, layout = time_path(lbm, ns, rt, lbm.LBM_PATH_FUSED, args.steps, args.warmup, extra)
     kern = kernel_bandwidth(kern, sites, lx, ly)
@@ -198,6 +212,15 @@ def main() -> int:
         separate = {"mlups": sites * args.steps / w2 / 1e6, "ms_per_step": w2 / args.steps * 1e3,
                     "kernels": k2}
         log(f"separate: {separate['mlups']:.1f} MLUPS")
+
+    log(f"fused path, FP32 storage {lx}x{ly}: {args.warmup} warmup + {args.steps} timed steps")
+    w3, k3, c3, _ = time_path(lbm, ns, rt, lbm.LBM_PATH_FUSED, args.steps, args.warmup,
+                              dict(extra, storage=lbm.LBM_FP32))
+    k3 = kernel_bandwidth(k3, sites, lx, ly, elem_bytes=4)
+    fp32 = {"mlups": sites * args.steps / w3 / 1e6, "ms_per_step": w3 / args.steps * 1e3,
+            "speedup_vs_fp64": (sites * args.steps / w3) / (sites * args.steps / wall),
+            "kernels": k3}
+    log(f"fp32 storage: {fp32['mlups']:.1f} MLUPS, fused kernel {k3['fused']['gbs']:.0f} GB/s")
 
     fk = kern["fused"]
     traffic = measured_traffic(lx, ly)
@@ -221,7 +244,7 @@ def main() -> int:
                        "nx": layout[0], "ny_pitch": layout[1], "plane_elems": layout[2],
                        "block": args.block or 256}},
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kern, "separate": separate,
-        "copy_reference": copy,
+        "bandwidth_probe": copy, "fp32_storage": fp32,
         "paper_equivalent_gflops": 6472 * sites * args.steps / wall / 1e9,
     }
     print(json.dumps(out), flush=True)

@@ -54,8 +54,10 @@ typedef enum {
   LBM_ESTATE = -4   /* lattice not initialised (init_rt / set_populations) */
 } lbm_status;
 
-/* Storage type of the populations. */
-typedef enum { LBM_FP64 = 0 } lbm_storage;
+/* Storage type of the populations.  Arithmetic is binary64 in both cases;
+ * LBM_FP32 widens each population exactly on load and rounds it to the
+ * nearest binary32 on store, halving the bytes moved per step. */
+typedef enum { LBM_FP64 = 0, LBM_FP32 = 1 } lbm_storage;
 
 /* Kernel sequence of lbm_step (Sec. 2 kernel list; fusion as in Sec. 5). */
 typedef enum {
@@ -181,6 +183,21 @@ int lbm_tables(int32_t *e, int32_t *opp, double *w, double *r);
 /* Wall factors K_l(T) = w_l [1 + th (C_l-2)/2 + th^2 (C_l^2 - 8 C_l + 8)/8],
  * th = T - 1, C_l = r^2 |e_l|^2, as bc applies them (host only). */
 int lbm_wall_factors(double t_wall, double out[LBM_NPOP]);
+
+/* Bandwidth probe: the copy micro-benchmark of Sec. 4 (Fig. misalignment)
+ * that chose pull over push.  Copies between two caller device buffers of
+ * `bytes` bytes (a multiple of 16, both 16-byte aligned) on `stream`,
+ * asynchronously:
+ *   LBM_PROBE_COPY: dst[i] = src[i], 16 bytes per lane, all bytes;
+ *   LBM_PROBE_MRAW: dst[64 + i] = src[64 + i + shift] (misaligned read);
+ *   LBM_PROBE_ARMW: dst[64 + i + shift] = src[64 + i] (misaligned write);
+ * for MRAW/ARMW elements are doubles, i < bytes / 8 - 128 and |shift| <= 64,
+ * so every access stays inside both buffers.  bytes >= 2048.  It touches no
+ * lattice state.
+ * Errors: EINVAL (NULL, misaligned, bad mode or shift), EDEVICE. */
+typedef enum { LBM_PROBE_COPY = 0, LBM_PROBE_MRAW = 1, LBM_PROBE_ARMW = 2 } lbm_probe;
+int lbm_probe_bandwidth(int32_t mode, const void *src, void *dst, size_t bytes, int32_t shift,
+                        void *stream);
 
 /* Reason of the last failure on h, or of the last failed lbm_create /
  * lbm_required_bytes on this thread when h is NULL.  Never NULL. */

@@ -317,6 +317,31 @@ def step(f: np.ndarray, cfg) -> np.ndarray:
     return collide(g, cfg.tau, cfg.gx, cfg.gy)
 
 
+def stored(f: np.ndarray, storage: str) -> np.ndarray:
+    """Values as held in memory: binary64 unchanged, or rounded to the
+    nearest binary32 (ties to even) and read back exactly."""
+    if storage == "fp64":
+        return f
+    if storage == "fp32":
+        return f.astype(np.float32).astype(np.float64)
+    raise ValueError(storage)
+
+
+def step_stored(f: np.ndarray, cfg, storage: str, fused: bool) -> np.ndarray:
+    """One step when populations are kept in `storage` between kernels.
+
+    Arithmetic is binary64; each kernel that writes populations rounds
+    them to the storage type.  The separate sequence stores after bc and
+    after collide (propagate only moves stored values); the fused kernel
+    stores once, after collide.
+    """
+    g = propagate(f)
+    g = bc(g, cfg.t_bottom, cfg.t_top)
+    if not fused:
+        g = stored(g, storage)
+    return stored(collide(g, cfg.tau, cfg.gx, cfg.gy), storage)
+
+
 def run(f: np.ndarray, cfg, n: int) -> np.ndarray:
     for _ in range(n):
         f = step(f, cfg)

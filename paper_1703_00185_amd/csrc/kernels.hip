@@ -35,11 +35,16 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
   return xcd * q + (xcd < r ? xcd : r) + idx;
 }
 
-__device__ __forceinline__ double ld(const double* base, unsigned byte_off) {
-  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byte_off);
+// Population storage: binary64, or binary32 widened exactly on load and
+// rounded to nearest on store.  All arithmetic is binary64 either way.
+// Offsets are in bytes from a wavefront-uniform base.
+template <class S>
+__device__ __forceinline__ double ld(const S* base, unsigned byte_off) {
+  return static_cast<double>(*reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + byte_off));
 }
-__device__ __forceinline__ void st(double* base, unsigned byte_off, double v) {
-  *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off) = v;
+template <class S>
+__device__ __forceinline__ void st(S* base, unsigned byte_off, double v) {
+  *reinterpret_cast<S*>(reinterpret_cast<char*>(base) + byte_off) = static_cast<S>(v);
 }
 
 // acc + k * v for a small integer k known after unrolling.
@@ -192,19 +197,21 @@ __device__ __forceinline__ bool interior_wave(const Geometry& g, int ywave) {
 // x - e_lx < 0 or >= Lx read the halo columns filled by pbc.  Interior
 // form: the per-population offset is uniform and the per-lane byte offset
 // is shared by all 37 loads.
-__device__ __forceinline__ void gather_interior(const Geometry& g, const double* __restrict__ src,
+template <class S>
+__device__ __forceinline__ void gather_interior(const Geometry& g, const S* __restrict__ src,
                                                 int x, int y, double (&f)[NPOP]) {
-  const unsigned off = static_cast<unsigned>((x + HALO) * g.ny + y) * 8u;
+  const unsigned off = static_cast<unsigned>((x + HALO) * g.ny + y) * static_cast<unsigned>(sizeof(S));
 #pragma unroll
   for (int l = 0; l < NPOP; ++l) {
-    const double* base = src + (static_cast<long long>(l) * g.plane - (EX[l] * g.ny + EY[l]));
+    const S* base = src + (static_cast<long long>(l) * g.plane - (EX[l] * g.ny + EY[l]));
     f[l] = ld(base, off);
   }
 }
 
 // General form, for wavefronts touching the walls: a source row beyond a
 // wall is replaced by the opposite population of the same site.
-__device__ __forceinline__ void gather_wall(const Geometry& g, const double* __restrict__ src,
+template <class S>
+__device__ __forceinline__ void gather_wall(const Geometry& g, const S* __restrict__ src,
                                             int x, int y, double (&f)[NPOP]) {
   const int X = x + HALO;
 #pragma unroll
@@ -214,20 +221,22 @@ __device__ __forceinline__ void gather_wall(const Geometry& g, const double* __r
     const long long idx = inside
         ? static_cast<long long>(l) * g.plane + static_cast<long long>(X - EX[l]) * g.ny + ys
         : static_cast<long long>(opp_of(l)) * g.plane + static_cast<long long>(X) * g.ny + y;
-    f[l] = src[idx];
+    f[l] = static_cast<double>(src[idx]);
   }
 }
 
-__device__ __forceinline__ void load_site(const Geometry& g, const double* __restrict__ src,
+template <class S>
+__device__ __forceinline__ void load_site(const Geometry& g, const S* __restrict__ src,
                                           int x, int y, double (&f)[NPOP]) {
-  const unsigned off = static_cast<unsigned>((x + HALO) * g.ny + y) * 8u;
+  const unsigned off = static_cast<unsigned>((x + HALO) * g.ny + y) * static_cast<unsigned>(sizeof(S));
 #pragma unroll
   for (int l = 0; l < NPOP; ++l) f[l] = ld(src + static_cast<long long>(l) * g.plane, off);
 }
 
-__device__ __forceinline__ void store_site(const Geometry& g, double* __restrict__ dst,
+template <class S>
+__device__ __forceinline__ void store_site(const Geometry& g, S* __restrict__ dst,
                                            int x, int y, const double (&f)[NPOP]) {
-  const unsigned off = static_cast<unsigned>((x + HALO) * g.ny + y) * 8u;
+  const unsigned off = static_cast<unsigned>((x + HALO) * g.ny + y) * static_cast<unsigned>(sizeof(S));
 #pragma unroll
   for (int l = 0; l < NPOP; ++l) st(dst + static_cast<long long>(l) * g.plane, off, f[l]);
 }
@@ -268,7 +277,8 @@ __constant__ HaloCopies kHalo = make_halo_copies();
 // pbc (Sec. 4): periodic x.  A population with e_x = k > 0 pulls from the
 // left halo columns X = 3 - d (d = 1..k), copies of physical column
 // Lx - d; one with e_x = -k pulls from X = Lx + 2 + d, copies of column d - 1.
-__global__ void __launch_bounds__(256) pbc_kernel(double* __restrict__ f, Geometry g) {
+template <class S>
+__global__ void __launch_bounds__(256) pbc_kernel(S* __restrict__ f, Geometry g) {
   const int y = blockIdx.x * 256 + threadIdx.x;
   if (y >= g.ly) return;
   const int c = blockIdx.y;
@@ -276,14 +286,14 @@ __global__ void __launch_bounds__(256) pbc_kernel(double* __restrict__ f, Geomet
   const int d = kHalo.d[c];
   const int dst_col = kHalo.right[c] ? g.lx + HALO - 1 + d : HALO - d;
   const int src_col = kHalo.right[c] ? HALO - 1 + d : g.lx + HALO - d;
-  double* plane = f + static_cast<long long>(l) * g.plane;
+  S* plane = f + static_cast<long long>(l) * g.plane;
   plane[static_cast<long long>(dst_col) * g.ny + y] = plane[static_cast<long long>(src_col) * g.ny + y];
 }
 
 // propagate (Sec. 4): pull gather into the other lattice copy.
-template <int BLOCK>
-__global__ void __launch_bounds__(BLOCK) propagate_kernel(const double* __restrict__ src,
-                                                          double* __restrict__ dst, Geometry g) {
+template <class S, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) propagate_kernel(const S* __restrict__ src,
+                                                          S* __restrict__ dst, Geometry g) {
   int x, y, ywave;
   lane_site<BLOCK>(g, x, y, ywave);
   double f[NPOP];
@@ -296,7 +306,8 @@ __global__ void __launch_bounds__(BLOCK) propagate_kernel(const double* __restri
 }
 
 // bc (Sec. 4): thermal walls, in place, on the 3 bottom and 3 top rows.
-__global__ void __launch_bounds__(256) bc_kernel(double* __restrict__ f, Geometry g, WallParams w) {
+template <class S>
+__global__ void __launch_bounds__(256) bc_kernel(S* __restrict__ f, Geometry g, WallParams w) {
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= g.lx * 2 * WALL_ROWS) return;
   const int x = t / (2 * WALL_ROWS);
@@ -310,9 +321,9 @@ __global__ void __launch_bounds__(256) bc_kernel(double* __restrict__ f, Geometr
 }
 
 // collide (Sec. 4): site-local collision into the other lattice copy.
-template <int BLOCK>
-__global__ void __launch_bounds__(BLOCK) collide_kernel(const double* __restrict__ src,
-                                                        double* __restrict__ dst, Geometry g,
+template <class S, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) collide_kernel(const S* __restrict__ src,
+                                                        S* __restrict__ dst, Geometry g,
                                                         CollideParams c) {
   int x, y, ywave;
   lane_site<BLOCK>(g, x, y, ywave);
@@ -326,9 +337,9 @@ __global__ void __launch_bounds__(BLOCK) collide_kernel(const double* __restrict
 // propagate + bc + collide in registers: one read and one write of every
 // population per step (the fusion the paper applies in Sec. 5, here on
 // every row, walls included, since bc is site-local).
-template <int BLOCK>
-__global__ void __launch_bounds__(BLOCK) fused_kernel(const double* __restrict__ src,
-                                                      double* __restrict__ dst, Geometry g,
+template <class S, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) fused_kernel(const S* __restrict__ src,
+                                                      S* __restrict__ dst, Geometry g,
                                                       CollideParams c, WallParams w) {
   int x, y, ywave;
   lane_site<BLOCK>(g, x, y, ywave);
@@ -346,7 +357,8 @@ __global__ void __launch_bounds__(BLOCK) fused_kernel(const double* __restrict__
 
 // Per-site rho, ux, uy, T into out[4][lx][ly] (Sec. 2 moment definitions;
 // D rho T = sum |c|^2 f - rho |u|^2).
-__global__ void __launch_bounds__(256) moments_kernel(const double* __restrict__ src,
+template <class S>
+__global__ void __launch_bounds__(256) moments_kernel(const S* __restrict__ src,
                                                       double* __restrict__ out, Geometry g) {
   const long long n = static_cast<long long>(g.lx) * g.ly;
   const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
@@ -383,8 +395,9 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
 
 // Conservation sums, pass 1: each work-group walks a fixed strided set of
 // sites and writes its 5 partial sums.
+template <class S>
 __global__ void __launch_bounds__(CONS_THREADS) conservation_partial_kernel(
-    const double* __restrict__ src, Geometry g, double* __restrict__ partials) {
+    const S* __restrict__ src, Geometry g, double* __restrict__ partials) {
   __shared__ double lds[CONS_THREADS / WAVE];
   const long long n = static_cast<long long>(g.lx) * g.ly;
   double acc[CONS_FIELDS] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -426,7 +439,8 @@ __global__ void __launch_bounds__(CONS_THREADS) conservation_final_kernel(
 
 // Gather the populations of n listed sites (coordinates checked on the
 // host): out[l * n + i] = f_l(xy[2i], xy[2i+1]).
-__global__ void __launch_bounds__(256) get_sites_kernel(const double* __restrict__ f, Geometry g,
+template <class S>
+__global__ void __launch_bounds__(256) get_sites_kernel(const S* __restrict__ f, Geometry g,
                                                         const int* __restrict__ xy, int n,
                                                         double* __restrict__ out) {
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -448,7 +462,8 @@ __device__ __forceinline__ double log_cosh(double z) {
 // Fourier modes, pressure in hydrostatic balance d ln p / dy = r gy / T
 // (closed-form integral from the interface, where p = 1), rho = p / T,
 // populations at the zero-velocity equilibrium rho K_l(T).
-__global__ void __launch_bounds__(256) init_rt_kernel(double* __restrict__ f, Geometry g, RtParams p) {
+template <class S>
+__global__ void __launch_bounds__(256) init_rt_kernel(S* __restrict__ f, Geometry g, RtParams p) {
   const long long n = static_cast<long long>(g.lx) * g.ly;
   const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
   if (i >= n) return;
@@ -466,7 +481,7 @@ __global__ void __launch_bounds__(256) init_rt_kernel(double* __restrict__ f, Ge
                           (p.tm * p.tm - p.a * p.a);
   const double rho = exp(R * p.gy * integral) / temp;
   const double th = temp - 1.0;
-  const unsigned off = static_cast<unsigned>((x + HALO) * g.ny + y) * 8u;
+  const unsigned off = static_cast<unsigned>((x + HALO) * g.ny + y) * static_cast<unsigned>(sizeof(S));
 #pragma unroll
   for (int l = 0; l < NPOP; ++l) {
     const double C = R2 * static_cast<double>(EX[l] * EX[l] + EY[l] * EY[l]);
@@ -475,87 +490,146 @@ __global__ void __launch_bounds__(256) init_rt_kernel(double* __restrict__ f, Ge
   }
 }
 
+// ---------------------------------------------------------------------------
+// Bandwidth probes
+// ---------------------------------------------------------------------------
+
+constexpr int PROBE_THREADS = 256;
+constexpr int PROBE_BLOCKS = 256 * 8;  // 8 work-groups per CU, grid-stride
+
+__global__ void __launch_bounds__(PROBE_THREADS) probe_copy_kernel(const double2* __restrict__ src,
+                                                                   double2* __restrict__ dst,
+                                                                   size_t n) {
+  for (size_t i = static_cast<size_t>(blockIdx.x) * PROBE_THREADS + threadIdx.x; i < n;
+       i += static_cast<size_t>(gridDim.x) * PROBE_THREADS)
+    dst[i] = src[i];
+}
+
+// dst[i + ws] = src[i + rs] for i in [0, n): one of rs, ws is the shift.
+__global__ void __launch_bounds__(PROBE_THREADS) probe_shift_kernel(const double* __restrict__ src,
+                                                                    double* __restrict__ dst,
+                                                                    size_t n, long long rs,
+                                                                    long long ws) {
+  for (size_t i = static_cast<size_t>(blockIdx.x) * PROBE_THREADS + threadIdx.x; i < n;
+       i += static_cast<size_t>(gridDim.x) * PROBE_THREADS)
+    dst[static_cast<long long>(i) + ws] = src[static_cast<long long>(i) + rs];
+}
+
 }  // namespace
 
-#define D2Q37_BLOCK_SWITCH(B, CALL)                         \
-  switch (B) {                                              \
-    case 64: { constexpr int BS = 64; CALL; break; }        \
-    case 128: { constexpr int BS = 128; CALL; break; }      \
-    case 256: { constexpr int BS = 256; CALL; break; }      \
-    case 512: { constexpr int BS = 512; CALL; break; }      \
-    case 1024: { constexpr int BS = 1024; CALL; break; }    \
+// Dispatch on storage type (S) and work-group size (BS).
+#define D2Q37_DISPATCH(G, ...)                                        \
+  switch ((G).storage) {                                               \
+    case STORAGE_F64: { using S = double; D2Q37_BLOCKS(G, __VA_ARGS__); break; } \
+    case STORAGE_F32: { using S = float; D2Q37_BLOCKS(G, __VA_ARGS__); break; }  \
+    default: return hipErrorInvalidValue;                              \
+  }
+#define D2Q37_BLOCKS(G, ...)                               \
+  switch ((G).block) {                                      \
+    case 64: { constexpr int BS = 64; __VA_ARGS__; break; }        \
+    case 128: { constexpr int BS = 128; __VA_ARGS__; break; }      \
+    case 256: { constexpr int BS = 256; __VA_ARGS__; break; }      \
+    case 512: { constexpr int BS = 512; __VA_ARGS__; break; }      \
+    case 1024: { constexpr int BS = 1024; __VA_ARGS__; break; }    \
     default: return hipErrorInvalidValue;                   \
   }
+#define D2Q37_STORAGE(G, ...)                                         \
+  switch ((G).storage) {                                               \
+    case STORAGE_F64: { using S = double; __VA_ARGS__; break; }               \
+    case STORAGE_F32: { using S = float; __VA_ARGS__; break; }                \
+    default: return hipErrorInvalidValue;                              \
+  }
 
-hipError_t launch_pbc(const Geometry& g, double* f, hipStream_t s) {
+hipError_t launch_pbc(const Geometry& g, void* f, hipStream_t s) {
   (void)hipGetLastError();
-  hipLaunchKernelGGL(pbc_kernel, dim3((g.ly + 255) / 256, 52), dim3(256), 0, s, f, g);
+  D2Q37_STORAGE(g, hipLaunchKernelGGL(pbc_kernel<S>, dim3((g.ly + 255) / 256, 52), dim3(256), 0, s,
+                                      static_cast<S*>(f), g));
   return hipGetLastError();
 }
 
-hipError_t launch_propagate(const Geometry& g, const double* src, double* dst, hipStream_t s) {
+hipError_t launch_propagate(const Geometry& g, const void* src, void* dst, hipStream_t s) {
   (void)hipGetLastError();
-  D2Q37_BLOCK_SWITCH(g.block, hipLaunchKernelGGL(propagate_kernel<BS>, dim3(g.lx * g.ny_blocks),
-                                                 dim3(BS), 0, s, src, dst, g));
+  D2Q37_DISPATCH(g, hipLaunchKernelGGL((propagate_kernel<S, BS>), dim3(g.lx * g.ny_blocks), dim3(BS),
+                                       0, s, static_cast<const S*>(src), static_cast<S*>(dst), g));
   return hipGetLastError();
 }
 
-hipError_t launch_bc(const Geometry& g, double* f, const WallParams& w, hipStream_t s) {
+hipError_t launch_bc(const Geometry& g, void* f, const WallParams& w, hipStream_t s) {
   const int n = g.lx * 2 * WALL_ROWS;
   (void)hipGetLastError();
-  hipLaunchKernelGGL(bc_kernel, dim3((n + 255) / 256), dim3(256), 0, s, f, g, w);
+  D2Q37_STORAGE(g, hipLaunchKernelGGL(bc_kernel<S>, dim3((n + 255) / 256), dim3(256), 0, s,
+                                      static_cast<S*>(f), g, w));
   return hipGetLastError();
 }
 
-hipError_t launch_collide(const Geometry& g, const double* src, double* dst,
-                          const CollideParams& c, hipStream_t s) {
+hipError_t launch_collide(const Geometry& g, const void* src, void* dst, const CollideParams& c,
+                          hipStream_t s) {
   (void)hipGetLastError();
-  D2Q37_BLOCK_SWITCH(g.block, hipLaunchKernelGGL(collide_kernel<BS>, dim3(g.lx * g.ny_blocks),
-                                                 dim3(BS), 0, s, src, dst, g, c));
+  D2Q37_DISPATCH(g, hipLaunchKernelGGL((collide_kernel<S, BS>), dim3(g.lx * g.ny_blocks), dim3(BS),
+                                       0, s, static_cast<const S*>(src), static_cast<S*>(dst), g, c));
   return hipGetLastError();
 }
 
-hipError_t launch_fused(const Geometry& g, const double* src, double* dst,
-                        const CollideParams& c, const WallParams& w, hipStream_t s) {
+hipError_t launch_fused(const Geometry& g, const void* src, void* dst, const CollideParams& c,
+                        const WallParams& w, hipStream_t s) {
   (void)hipGetLastError();
-  D2Q37_BLOCK_SWITCH(g.block, hipLaunchKernelGGL(fused_kernel<BS>, dim3(g.lx * g.ny_blocks),
-                                                 dim3(BS), 0, s, src, dst, g, c, w));
+  D2Q37_DISPATCH(g, hipLaunchKernelGGL((fused_kernel<S, BS>), dim3(g.lx * g.ny_blocks), dim3(BS), 0,
+                                       s, static_cast<const S*>(src), static_cast<S*>(dst), g, c, w));
   return hipGetLastError();
 }
 
-hipError_t launch_moments(const Geometry& g, const double* f, double* out, hipStream_t s) {
+hipError_t launch_moments(const Geometry& g, const void* f, double* out, hipStream_t s) {
   const long long n = static_cast<long long>(g.lx) * g.ly;
   (void)hipGetLastError();
-  hipLaunchKernelGGL(moments_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s,
-                     f, out, g);
+  D2Q37_STORAGE(g, hipLaunchKernelGGL(moments_kernel<S>, dim3(static_cast<unsigned>((n + 255) / 256)),
+                                      dim3(256), 0, s, static_cast<const S*>(f), out, g));
   return hipGetLastError();
 }
 
-hipError_t launch_conservation(const Geometry& g, const double* f, double* partials,
-                               double* result, hipStream_t s) {
+hipError_t launch_conservation(const Geometry& g, const void* f, double* partials, double* result,
+                               hipStream_t s) {
   (void)hipGetLastError();
-  hipLaunchKernelGGL(conservation_partial_kernel, dim3(CONS_BLOCKS), dim3(CONS_THREADS), 0, s, f, g,
-                     partials);
+  D2Q37_STORAGE(g, hipLaunchKernelGGL(conservation_partial_kernel<S>, dim3(CONS_BLOCKS),
+                                      dim3(CONS_THREADS), 0, s, static_cast<const S*>(f), g, partials));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  (void)hipGetLastError();
   hipLaunchKernelGGL(conservation_final_kernel, dim3(1), dim3(CONS_THREADS), 0, s, partials,
                      CONS_BLOCKS, result);
   return hipGetLastError();
 }
 
-hipError_t launch_get_sites(const Geometry& g, const double* f, const int* xy, int n, double* out,
+hipError_t launch_get_sites(const Geometry& g, const void* f, const int* xy, int n, double* out,
                             hipStream_t s) {
   (void)hipGetLastError();
-  hipLaunchKernelGGL(get_sites_kernel, dim3((n + 255) / 256), dim3(256), 0, s, f, g, xy, n, out);
+  D2Q37_STORAGE(g, hipLaunchKernelGGL(get_sites_kernel<S>, dim3((n + 255) / 256), dim3(256), 0, s,
+                                      static_cast<const S*>(f), g, xy, n, out));
   return hipGetLastError();
 }
 
-hipError_t launch_init_rt(const Geometry& g, double* f, const RtParams& p, hipStream_t s) {
+hipError_t launch_probe(int mode, const void* src, void* dst, size_t n16, int shift, hipStream_t s) {
+  (void)hipGetLastError();
+  if (mode == 0) {
+    hipLaunchKernelGGL(probe_copy_kernel, dim3(PROBE_BLOCKS), dim3(PROBE_THREADS), 0, s,
+                       static_cast<const double2*>(src), static_cast<double2*>(dst), n16);
+  } else {
+    // doubles: the aligned side is index i + 64 (a whole wavefront of
+    // doubles in), the misaligned side i + 64 + shift, i in [0, n - 128),
+    // so both stay inside [0, n) for |shift| <= 64.
+    const long long n = 2 * static_cast<long long>(n16);
+    const long long rs = mode == 1 ? 64 + shift : 64;
+    const long long ws = mode == 1 ? 64 : 64 + shift;
+    hipLaunchKernelGGL(probe_shift_kernel, dim3(PROBE_BLOCKS), dim3(PROBE_THREADS), 0, s,
+                       static_cast<const double*>(src), static_cast<double*>(dst),
+                       static_cast<size_t>(n - 128), rs, ws);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_init_rt(const Geometry& g, void* f, const RtParams& p, hipStream_t s) {
   const long long n = static_cast<long long>(g.lx) * g.ly;
   (void)hipGetLastError();
-  hipLaunchKernelGGL(init_rt_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s,
-                     f, g, p);
+  D2Q37_STORAGE(g, hipLaunchKernelGGL(init_rt_kernel<S>, dim3(static_cast<unsigned>((n + 255) / 256)),
+                                      dim3(256), 0, s, static_cast<S*>(f), g, p));
   return hipGetLastError();
 }
 

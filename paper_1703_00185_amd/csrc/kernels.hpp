@@ -12,8 +12,12 @@ namespace d2q37 {
 // each side (physical column x is X = x + 3), y in [0, ny) is the row, with
 // rows >= ly being padding that is never read.  Element (l, X, y) sits at
 // l * plane + X * ny + y.
+// Population storage types.
+enum Storage : int { STORAGE_F64 = 0, STORAGE_F32 = 1 };
+
 struct Geometry {
   int lx, ly;
+  int storage;       // Storage: element type of the population planes
   int ny;            // column pitch, elements
   int block;         // work-group size of the lattice kernels
   int ny_blocks;     // ceil(ly / block)
@@ -50,18 +54,24 @@ constexpr int CONS_BLOCKS = 1024;  // work-groups of the conservation pass
 constexpr int CONS_THREADS = 256;
 constexpr int CONS_FIELDS = 5;     // mass, jx, jy, energy, non-finite count
 
-hipError_t launch_pbc(const Geometry& g, double* f, hipStream_t s);
-hipError_t launch_propagate(const Geometry& g, const double* src, double* dst, hipStream_t s);
-hipError_t launch_bc(const Geometry& g, double* f, const WallParams& w, hipStream_t s);
-hipError_t launch_collide(const Geometry& g, const double* src, double* dst,
-                          const CollideParams& c, hipStream_t s);
-hipError_t launch_fused(const Geometry& g, const double* src, double* dst,
-                        const CollideParams& c, const WallParams& w, hipStream_t s);
-hipError_t launch_moments(const Geometry& g, const double* f, double* out, hipStream_t s);
-hipError_t launch_conservation(const Geometry& g, const double* f, double* partials,
-                               double* result, hipStream_t s);
-hipError_t launch_get_sites(const Geometry& g, const double* f, const int* xy, int n, double* out,
+// Launchers: enqueue one kernel on stream s; the population pointers
+// point to planes of the geometry's storage type.
+hipError_t launch_pbc(const Geometry& g, void* f, hipStream_t s);
+hipError_t launch_propagate(const Geometry& g, const void* src, void* dst, hipStream_t s);
+hipError_t launch_bc(const Geometry& g, void* f, const WallParams& w, hipStream_t s);
+hipError_t launch_collide(const Geometry& g, const void* src, void* dst, const CollideParams& c,
+                          hipStream_t s);
+hipError_t launch_fused(const Geometry& g, const void* src, void* dst, const CollideParams& c,
+                        const WallParams& w, hipStream_t s);
+hipError_t launch_moments(const Geometry& g, const void* f, double* out, hipStream_t s);
+hipError_t launch_conservation(const Geometry& g, const void* f, double* partials, double* result,
+                               hipStream_t s);
+hipError_t launch_get_sites(const Geometry& g, const void* f, const int* xy, int n, double* out,
                             hipStream_t s);
-hipError_t launch_init_rt(const Geometry& g, double* f, const RtParams& p, hipStream_t s);
+hipError_t launch_init_rt(const Geometry& g, void* f, const RtParams& p, hipStream_t s);
+
+// Copy probes (aligned copy, misaligned read / aligned write, aligned read /
+// misaligned write); n16 = bytes / 16, shift in doubles.
+hipError_t launch_probe(int mode, const void* src, void* dst, size_t n16, int shift, hipStream_t s);
 
 }  // namespace d2q37

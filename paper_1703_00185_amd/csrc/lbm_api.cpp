@@ -19,7 +19,7 @@ struct lbm_handle {
   lbm_config cfg{};
   Geometry geo{};
   size_t buf_bytes = 0;
-  double* buf[2] = {nullptr, nullptr};
+  char* buf[2] = {nullptr, nullptr};
   int cur = 0;  // buffer holding the current populations
   hipStream_t stream = nullptr;
   int device = 0;
@@ -61,6 +61,8 @@ constexpr long long kMaxPlaneElems = (1LL << 29);  // byte offsets inside a plan
 
 long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
 
+int elem_bytes(const Geometry& g) { return g.storage == STORAGE_F32 ? 4 : 8; }
+
 struct Layout {
   Geometry geo;
   size_t buf_bytes;
@@ -76,7 +78,8 @@ int make_layout(const lbm_config* c, Layout* out, std::string* why) {
   if (!std::isfinite(c->t_bottom) || !(c->t_bottom > 0.0) || !std::isfinite(c->t_top) ||
       !(c->t_top > 0.0))
     return *why = "wall temperatures must be finite and > 0", LBM_EINVAL;
-  if (c->storage != LBM_FP64) return *why = "storage: only LBM_FP64 is supported", LBM_EINVAL;
+  if (c->storage != LBM_FP64 && c->storage != LBM_FP32)
+    return *why = "storage must be LBM_FP64 or LBM_FP32", LBM_EINVAL;
   if (c->path != LBM_PATH_SEPARATE && c->path != LBM_PATH_FUSED)
     return *why = "path must be LBM_PATH_SEPARATE or LBM_PATH_FUSED", LBM_EINVAL;
   const int block = c->block == 0 ? 256 : c->block;
@@ -88,6 +91,7 @@ int make_layout(const lbm_config* c, Layout* out, std::string* why) {
   Geometry g{};
   g.lx = c->lx;
   g.ly = c->ly;
+  g.storage = c->storage == LBM_FP32 ? STORAGE_F32 : STORAGE_F64;
   g.block = block;
   const long long ny = round_up(c->ly, 64) + (c->ny_pad > 0 ? c->ny_pad : 0);
   const long long nx = static_cast<long long>(c->lx) + 2 * HALO;
@@ -99,7 +103,8 @@ int make_layout(const lbm_config* c, Layout* out, std::string* why) {
     return *why = "too many work-groups", LBM_EINVAL;
   g.plane = round_up(nx * ny, 64) + (c->plane_pad > 0 ? c->plane_pad : 0);
   out->geo = g;
-  out->buf_bytes = static_cast<size_t>(round_up(static_cast<long long>(NPOP) * g.plane * 8, 256));
+  out->buf_bytes =
+      static_cast<size_t>(round_up(static_cast<long long>(NPOP) * g.plane * elem_bytes(g), 256));
   return LBM_OK;
 }
 
@@ -114,8 +119,14 @@ struct DeviceGuard {
   }
 };
 
-double* other(lbm_handle* h) { return h->buf[h->cur ^ 1]; }
-double* current(lbm_handle* h) { return h->buf[h->cur]; }
+char* other(lbm_handle* h) { return h->buf[h->cur ^ 1]; }
+char* current(lbm_handle* h) { return h->buf[h->cur]; }
+double* scratch(lbm_handle* h) { return reinterpret_cast<double*>(other(h)); }
+
+// Byte offset of physical column 0 of population l.
+size_t plane_col0(const Geometry& g, int l) {
+  return (static_cast<size_t>(l) * g.plane + static_cast<size_t>(HALO) * g.ny) * elem_bytes(g);
+}
 
 // Launch with optional timing events around it.
 template <class F>
@@ -229,8 +240,8 @@ int lbm_create(const lbm_config* cfg, void* dev_mem, size_t dev_bytes, void* str
   h->cfg = *cfg;
   h->geo = L.geo;
   h->buf_bytes = L.buf_bytes;
-  h->buf[0] = static_cast<double*>(dev_mem);
-  h->buf[1] = reinterpret_cast<double*>(static_cast<char*>(dev_mem) + L.buf_bytes);
+  h->buf[0] = static_cast<char*>(dev_mem);
+  h->buf[1] = static_cast<char*>(dev_mem) + L.buf_bytes;
   h->stream = static_cast<hipStream_t>(stream);
   h->device = attr.device;
   const double tau = cfg->tau;
@@ -313,13 +324,13 @@ int lbm_moments(lbm_handle* h, double* rho, double* ux, double* uy, double* T) {
   if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
   if (!h->ready) return fail(h, LBM_ESTATE, "lattice not initialised");
   DeviceGuard dg(h->device);
-  double* scratch = other(h);
-  LBM_HIP(h, launch_moments(h->geo, current(h), scratch, h->stream));
+  double* tmp = scratch(h);
+  LBM_HIP(h, launch_moments(h->geo, current(h), tmp, h->stream));
   const size_t n = static_cast<size_t>(h->geo.lx) * h->geo.ly;
   double* outs[4] = {rho, ux, uy, T};
   for (int k = 0; k < 4; ++k)
     if (outs[k])
-      LBM_HIP(h, hipMemcpyAsync(outs[k], scratch + k * n, n * sizeof(double), hipMemcpyDeviceToHost,
+      LBM_HIP(h, hipMemcpyAsync(outs[k], tmp + k * n, n * sizeof(double), hipMemcpyDeviceToHost,
                                 h->stream));
   LBM_HIP(h, hipStreamSynchronize(h->stream));
   return LBM_OK;
@@ -330,7 +341,7 @@ int lbm_conservation(lbm_handle* h, double out[5]) {
   if (!out) return fail(h, LBM_EINVAL, "out is NULL");
   if (!h->ready) return fail(h, LBM_ESTATE, "lattice not initialised");
   DeviceGuard dg(h->device);
-  double* partials = other(h);
+  double* partials = scratch(h);
   double* result = partials + CONS_BLOCKS * CONS_FIELDS;
   LBM_HIP(h, launch_conservation(h->geo, current(h), partials, result, h->stream));
   LBM_HIP(h, hipMemcpyAsync(out, result, CONS_FIELDS * sizeof(double), hipMemcpyDeviceToHost,
@@ -345,12 +356,18 @@ int lbm_get_populations(lbm_handle* h, double* host) {
   if (!h->ready) return fail(h, LBM_ESTATE, "lattice not initialised");
   DeviceGuard dg(h->device);
   const Geometry& g = h->geo;
-  const size_t row = static_cast<size_t>(g.ly) * sizeof(double);
+  const size_t eb = elem_bytes(g);
+  const size_t n = static_cast<size_t>(g.lx) * g.ly;
+  std::vector<float> tmp(g.storage == STORAGE_F32 ? n : 0);
   for (int l = 0; l < NPOP; ++l) {
-    const double* src = current(h) + l * g.plane + static_cast<long long>(HALO) * g.ny;
-    LBM_HIP(h, hipMemcpy2DAsync(host + static_cast<size_t>(l) * g.lx * g.ly, row, src,
-                                static_cast<size_t>(g.ny) * sizeof(double), row, g.lx,
-                                hipMemcpyDeviceToHost, h->stream));
+    double* dst = host + static_cast<size_t>(l) * n;
+    void* stage = g.storage == STORAGE_F32 ? static_cast<void*>(tmp.data()) : static_cast<void*>(dst);
+    LBM_HIP(h, hipMemcpy2DAsync(stage, g.ly * eb, current(h) + plane_col0(g, l), g.ny * eb, g.ly * eb,
+                                g.lx, hipMemcpyDeviceToHost, h->stream));
+    if (g.storage == STORAGE_F32) {
+      LBM_HIP(h, hipStreamSynchronize(h->stream));
+      for (size_t i = 0; i < n; ++i) dst[i] = static_cast<double>(tmp[i]);  // exact widening
+    }
   }
   LBM_HIP(h, hipStreamSynchronize(h->stream));
   return LBM_OK;
@@ -361,12 +378,19 @@ int lbm_set_populations(lbm_handle* h, const double* host) {
   if (!host) return fail(h, LBM_EINVAL, "host is NULL");
   DeviceGuard dg(h->device);
   const Geometry& g = h->geo;
-  const size_t row = static_cast<size_t>(g.ly) * sizeof(double);
+  const size_t eb = elem_bytes(g);
+  const size_t n = static_cast<size_t>(g.lx) * g.ly;
+  std::vector<float> tmp(g.storage == STORAGE_F32 ? n : 0);
   for (int l = 0; l < NPOP; ++l) {
-    double* dst = current(h) + l * g.plane + static_cast<long long>(HALO) * g.ny;
-    LBM_HIP(h, hipMemcpy2DAsync(dst, static_cast<size_t>(g.ny) * sizeof(double),
-                                host + static_cast<size_t>(l) * g.lx * g.ly, row, row, g.lx,
-                                hipMemcpyHostToDevice, h->stream));
+    const double* src = host + static_cast<size_t>(l) * n;
+    const void* stage = src;
+    if (g.storage == STORAGE_F32) {
+      for (size_t i = 0; i < n; ++i) tmp[i] = static_cast<float>(src[i]);  // round to nearest even
+      stage = tmp.data();
+    }
+    LBM_HIP(h, hipMemcpy2DAsync(current(h) + plane_col0(g, l), g.ny * eb, stage, g.ly * eb, g.ly * eb,
+                                g.lx, hipMemcpyHostToDevice, h->stream));
+    if (g.storage == STORAGE_F32) LBM_HIP(h, hipStreamSynchronize(h->stream));
   }
   LBM_HIP(h, hipStreamSynchronize(h->stream));
   h->ready = true;
@@ -390,7 +414,7 @@ int lbm_get_sites(lbm_handle* h, int32_t n, const int32_t* xs, const int32_t* ys
     xy[2 * i + 1] = ys[i];
   }
   DeviceGuard dg(h->device);
-  double* scratch_out = other(h);
+  double* scratch_out = scratch(h);
   int* scratch_xy = reinterpret_cast<int*>(scratch_out + static_cast<size_t>(NPOP) * n);
   LBM_HIP(h, hipMemcpyAsync(scratch_xy, xy.data(), xy.size() * sizeof(int), hipMemcpyHostToDevice,
                             h->stream));
@@ -452,6 +476,20 @@ int lbm_tables(int32_t* e, int32_t* opp, double* w, double* r) {
 int lbm_wall_factors(double t_wall, double out[LBM_NPOP]) {
   if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
   for (int l = 0; l < NPOP; ++l) out[l] = wall_factor(l, t_wall);
+  return LBM_OK;
+}
+
+int lbm_probe_bandwidth(int32_t mode, const void* src, void* dst, size_t bytes, int32_t shift,
+                        void* stream) {
+  if (!src || !dst) return fail(nullptr, LBM_EINVAL, "src/dst are NULL");
+  if (mode < LBM_PROBE_COPY || mode > LBM_PROBE_ARMW) return fail(nullptr, LBM_EINVAL, "bad probe mode");
+  if (bytes % 16 != 0 || bytes < 2048)
+    return fail(nullptr, LBM_EINVAL, "bytes must be a multiple of 16 and at least 2048");
+  if (reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 16)
+    return fail(nullptr, LBM_EINVAL, "src/dst must be 16-byte aligned");
+  if (shift < -64 || shift > 64) return fail(nullptr, LBM_EINVAL, "shift must be within [-64, 64]");
+  if (mode == LBM_PROBE_COPY && shift != 0) return fail(nullptr, LBM_EINVAL, "COPY takes shift 0");
+  LBM_HIP(nullptr, launch_probe(mode, src, dst, bytes / 16, shift, static_cast<hipStream_t>(stream)));
   return LBM_OK;
 }
 

@@ -14,12 +14,15 @@ from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_int32, c_int64, 
 
 import numpy as np
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libd2q37.so")
+# The in-tree build; PAPER_1703_00185_AMD_LIB may name another build of the
+# same sources (used to compare tuning variants side by side).
+LIB_PATH = os.environ.get("PAPER_1703_00185_AMD_LIB") or os.path.join(
+    os.path.dirname(os.path.abspath(__file__)), "libd2q37.so")
 
 NPOP = 37
 MAX_MODES = 32
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ESTATE = 0, -1, -2, -3, -4
-LBM_FP64 = 0
+LBM_FP64, LBM_FP32 = 0, 1
 LBM_PATH_SEPARATE, LBM_PATH_FUSED = 0, 1
 (LBM_PHASE_PBC, LBM_PHASE_PROPAGATE, LBM_PHASE_BC, LBM_PHASE_COLLIDE,
  LBM_PHASE_FUSED) = range(5)
@@ -77,6 +80,7 @@ def load():
         "lbm_layout": (c_int, [H, c_void_p]),
         "lbm_tables": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
         "lbm_wall_factors": (c_int, [c_double, c_void_p]),
+        "lbm_probe_bandwidth": (c_int, [c_int32, c_void_p, c_void_p, c_size_t, c_int32, c_void_p]),
         "lbm_last_error": (c_char_p, [H]),
         "lbm_destroy": (None, [H]),
     }
@@ -212,6 +216,14 @@ def lbm_wall_factors(t_wall: float) -> np.ndarray:
     out = np.zeros(NPOP, dtype=np.float64)
     _check(load().lbm_wall_factors(t_wall, _ptr(out)))
     return out
+
+
+LBM_PROBE_COPY, LBM_PROBE_MRAW, LBM_PROBE_ARMW = 0, 1, 2
+
+
+def lbm_probe_bandwidth(mode: int, src: int, dst: int, nbytes: int, shift: int, stream: int) -> None:
+    _check(load().lbm_probe_bandwidth(mode, c_void_p(src), c_void_p(dst), nbytes, shift,
+                                      c_void_p(stream)))
 
 
 def lbm_destroy(h) -> None:

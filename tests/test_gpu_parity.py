@@ -276,3 +276,38 @@ def test_host_memory_pointer_rejected():
     with pytest.raises(lbm.LbmError) as ei:
         lbm.lbm_create(cfg, addr, need, 0)
     assert ei.value.status in (lbm.LBM_EINVAL, lbm.LBM_EDEVICE)
+
+
+@pytest.mark.parametrize("mode,shift", [(0, 0), (1, 3), (1, -3), (1, 0), (2, 1), (2, -2), (2, 64),
+                                        (1, -64)])
+def test_bandwidth_probe_copies(mode, shift):
+    import torch
+    n = 4096
+    src = torch.arange(n // 8, dtype=torch.float64, device="cuda")
+    dst = torch.full((n // 8,), -1.0, dtype=torch.float64, device="cuda")
+    lbm.lbm_probe_bandwidth(mode, src.data_ptr(), dst.data_ptr(), n, shift,
+                            torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    s, d = src.cpu().numpy(), dst.cpu().numpy()
+    if mode == 0:
+        assert np.array_equal(d, s)
+        return
+    m = n // 8 - 128
+    i = np.arange(m)
+    rs, ws = (64 + shift, 64) if mode == 1 else (64, 64 + shift)
+    assert np.array_equal(d[i + ws], s[i + rs])
+    untouched = np.setdiff1d(np.arange(n // 8), i + ws)
+    assert np.all(d[untouched] == -1.0)
+
+
+def test_bandwidth_probe_rejects_bad_arguments():
+    import torch
+    buf = torch.empty(4096, dtype=torch.uint8, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    for args in [(3, 0), (0, 1), (1, 65)]:
+        with pytest.raises(lbm.LbmError):
+            lbm.lbm_probe_bandwidth(args[0], buf.data_ptr(), buf.data_ptr(), 4096, args[1], st)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_probe_bandwidth(0, buf.data_ptr() + 8, buf.data_ptr(), 2048, 0, st)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_probe_bandwidth(0, buf.data_ptr(), buf.data_ptr(), 1024, 0, st)

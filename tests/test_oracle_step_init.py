@@ -99,3 +99,25 @@ def test_initial_state_is_rest_equilibrium():
     assert np.max(np.abs(T2 - T)) < 1e-14
     # hot (dense-is-light) layer at the bottom, cold at the top
     assert T[0, 0] > 1.04 and T[0, -1] < 0.96
+
+
+def test_stored_step_reduces_to_step_in_fp64():
+    cfg = inputs.rt_config(8, 20)
+    f = oracle.init_rt(8, 20, cfg, inputs.rt_perturbation(1, 20))
+    for fused in (True, False):
+        assert np.array_equal(oracle.step_stored(f, cfg, "fp64", fused), oracle.step(f, cfg))
+
+
+def test_fp32_storage_rounds_every_value_once():
+    """The FP32 result is the binary32 rounding of the FP64 step (fused),
+    so it is within half a binary32 ulp of it and exactly representable."""
+    cfg = inputs.rt_config(8, 20)
+    f = oracle.stored(oracle.init_rt(8, 20, cfg, inputs.rt_perturbation(1, 20)), "fp32")
+    exact = oracle.step(f, cfg)
+    got = oracle.step_stored(f, cfg, "fp32", True)
+    assert np.array_equal(got.astype(np.float32).astype(np.float64), got)
+    half_ulp = np.spacing(np.abs(got).astype(np.float32)).astype(np.float64) / 2
+    assert np.all(np.abs(got - exact) <= half_ulp)
+    # interior rows equal for both sequences; wall rows see one extra rounding
+    sep = oracle.step_stored(f, cfg, "fp32", False)
+    assert np.array_equal(sep[:, :, 3:17], got[:, :, 3:17])
