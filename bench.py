@@ -213,14 +213,17 @@ def main() -> int:
                     "kernels": k2}
         log(f"separate: {separate['mlups']:.1f} MLUPS")
 
-    log(f"fused path, FP32 storage {lx}x{ly}: {args.warmup} warmup + {args.steps} timed steps")
-    w3, k3, c3, _ = time_path(lbm, ns, rt, lbm.LBM_PATH_FUSED, args.steps, args.warmup,
-                              dict(extra, storage=lbm.LBM_FP32))
-    k3 = kernel_bandwidth(k3, sites, lx, ly, elem_bytes=4)
-    fp32 = {"mlups": sites * args.steps / w3 / 1e6, "ms_per_step": w3 / args.steps * 1e3,
-            "speedup_vs_fp64": (sites * args.steps / w3) / (sites * args.steps / wall),
-            "kernels": k3}
-    log(f"fp32 storage: {fp32['mlups']:.1f} MLUPS, fused kernel {k3['fused']['gbs']:.0f} GB/s")
+    reduced = {}
+    for name, storage, eb in (("fp32", lbm.LBM_FP32, 4), ("fp16dev", lbm.LBM_FP16DEV, 2)):
+        log(f"fused path, {name} storage {lx}x{ly}: {args.warmup} warmup + {args.steps} timed steps")
+        w3, k3, c3, _ = time_path(lbm, ns, rt, lbm.LBM_PATH_FUSED, args.steps, args.warmup,
+                                  dict(extra, storage=storage))
+        k3 = kernel_bandwidth(k3, sites, lx, ly, elem_bytes=eb)
+        reduced[name] = {"mlups": sites * args.steps / w3 / 1e6, "ms_per_step": w3 / args.steps * 1e3,
+                         "speedup_vs_fp64": wall / w3, "bytes_per_site": 2 * 37 * eb,
+                         "kernels": k3}
+        log(f"{name} storage: {reduced[name]['mlups']:.1f} MLUPS, "
+            f"fused kernel {k3['fused']['gbs']:.0f} GB/s")
 
     fk = kern["fused"]
     traffic = measured_traffic(lx, ly)
@@ -244,7 +247,7 @@ def main() -> int:
                        "nx": layout[0], "ny_pitch": layout[1], "plane_elems": layout[2],
                        "block": args.block or 256}},
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kern, "separate": separate,
-        "bandwidth_probe": copy, "fp32_storage": fp32,
+        "bandwidth_probe": copy, "reduced_storage": reduced,
         "paper_equivalent_gflops": 6472 * sites * args.steps / wall / 1e9,
     }
     print(json.dumps(out), flush=True)

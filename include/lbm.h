@@ -54,10 +54,14 @@ typedef enum {
   LBM_ESTATE = -4   /* lattice not initialised (init_rt / set_populations) */
 } lbm_status;
 
-/* Storage type of the populations.  Arithmetic is binary64 in both cases;
- * LBM_FP32 widens each population exactly on load and rounds it to the
- * nearest binary32 on store, halving the bytes moved per step. */
-typedef enum { LBM_FP64 = 0, LBM_FP32 = 1 } lbm_storage;
+/* Storage type of the populations.  Arithmetic is binary64 for all.
+ *   LBM_FP32: widened exactly on load, rounded to nearest binary32 on store.
+ *   LBM_FP16DEV: binary16 scaled deviation from a per-row reference,
+ *     c = w_l rho_ref(y): stored d = f16(f32((f - c) * (w_l^-1 rho_ref(y)^-1))),
+ *     read back as c (1 + d).  rho_ref comes from lbm_init_rt (density of
+ *     the flat-interface state) or lbm_set_reference.
+ * Bytes per population: 8, 4, 2. */
+typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16DEV = 2 } lbm_storage;
 
 /* Kernel sequence of lbm_step (Sec. 2 kernel list; fusion as in Sec. 5). */
 typedef enum {
@@ -110,8 +114,8 @@ typedef struct {
  * walls 1.05 (bottom) / 0.95 (top), FP64, fused path, default tiling. */
 int lbm_config_default(lbm_config *cfg, int32_t lx, int32_t ly);
 
-/* Bytes of device memory needed for cfg (two lattice copies with halos);
- * 0 if cfg is invalid. */
+/* Bytes of device memory needed for cfg (two lattice copies with halos,
+ * plus the reference rows of deviation storage); 0 if cfg is invalid. */
 size_t lbm_required_bytes(const lbm_config *cfg);
 
 /* Bind a lattice to caller memory dev_mem (dev_bytes long) and to the HIP
@@ -152,8 +156,9 @@ int lbm_moments(lbm_handle *h, double *rho, double *ux, double *uy, double *T);
 int lbm_conservation(lbm_handle *h, double out[5]);
 
 /* Copy the current populations to / from a host array [37][Lx][Ly]
- * (checkpoint and restore; restore marks the state initialised).
- * Synchronise the stream. */
+ * (checkpoint and restore; restore marks the state initialised), through
+ * the storage codec, one plane at a time staged in the idle lattice copy.
+ * Synchronise the stream.  Deviation storage needs a reference first. */
 int lbm_get_populations(lbm_handle *h, double *host);
 int lbm_set_populations(lbm_handle *h, const double *host);
 
@@ -162,6 +167,13 @@ int lbm_set_populations(lbm_handle *h, const double *host);
  * on the host: EINVAL otherwise).  n may be at most lbm_layout()[3] / 304.
  * Uses the idle lattice copy as scratch.  Synchronises the stream. */
 int lbm_get_sites(lbm_handle *h, int32_t n, const int32_t *xs, const int32_t *ys, double *out);
+
+/* Deviation storage only: set / read the per-row reference density
+ * rho_ref[Ly] (host arrays, finite and > 0).  Setting it invalidates the
+ * stored state (set populations or init again).  Errors: EINVAL (other
+ * storage, bad values), ESTATE (no reference yet, get only). */
+int lbm_set_reference(lbm_handle *h, const double *rho_ref);
+int lbm_get_reference(lbm_handle *h, double *rho_ref);
 
 /* Per-phase kernel timing with HIP events recorded on the bound stream
  * around every launch while enabled.  lbm_read_timing synchronises the

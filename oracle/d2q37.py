@@ -317,29 +317,54 @@ def step(f: np.ndarray, cfg) -> np.ndarray:
     return collide(g, cfg.tau, cfg.gx, cfg.gy)
 
 
-def stored(f: np.ndarray, storage: str) -> np.ndarray:
-    """Values as held in memory: binary64 unchanged, or rounded to the
-    nearest binary32 (ties to even) and read back exactly."""
+def encode_fp16dev(f: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """Binary16 scaled deviations d of f[37, Lx, Ly] from c = w_l ref(y):
+    q = (f - c) * (w_l^-1 * ref(y)^-1) in binary64, rounded to binary32 and
+    then to binary16 (nearest, ties to even, at each rounding)."""
+    k = constants()
+    c = k.w[:, None, None] * ref[None, None, :]
+    inv = (1.0 / k.w)[:, None, None] * (1.0 / ref)[None, None, :]
+    q = (f - c) * inv
+    return q.astype(np.float32).astype(np.float16)
+
+
+def decode_fp16dev(d: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """Populations c (1 + d) from binary16 deviations (1 + d is exact)."""
+    k = constants()
+    c = k.w[:, None, None] * ref[None, None, :]
+    return c * (1.0 + d.astype(np.float64))
+
+
+def stored(f: np.ndarray, storage: str, ref=None) -> np.ndarray:
+    """Values as held in memory and read back: binary64 unchanged; binary32
+    rounded to nearest (ties to even); binary16 deviations from the per-row
+    reference density `ref` (encode_fp16dev, then decode_fp16dev)."""
     if storage == "fp64":
         return f
     if storage == "fp32":
         return f.astype(np.float32).astype(np.float64)
+    if storage == "fp16dev":
+        return decode_fp16dev(encode_fp16dev(f, ref), ref)
     raise ValueError(storage)
 
 
-def step_stored(f: np.ndarray, cfg, storage: str, fused: bool) -> np.ndarray:
+def step_stored(f: np.ndarray, cfg, storage: str, fused: bool, ref=None) -> np.ndarray:
     """One step when populations are kept in `storage` between kernels.
 
-    Arithmetic is binary64; each kernel that writes populations rounds
-    them to the storage type.  The separate sequence stores after bc and
-    after collide (propagate only moves stored values); the fused kernel
-    stores once, after collide.
+    Arithmetic is binary64; each kernel that writes populations stores
+    them in the storage type.  The separate sequence stores after
+    propagate, after bc and after collide; the fused kernel stores once,
+    after collide.  (Propagate only moves values, so its store changes
+    nothing unless the encoding depends on the row, as the deviation
+    storage's reference does.)
     """
     g = propagate(f)
+    if not fused:
+        g = stored(g, storage, ref)
     g = bc(g, cfg.t_bottom, cfg.t_top)
     if not fused:
-        g = stored(g, storage)
-    return stored(collide(g, cfg.tau, cfg.gx, cfg.gy), storage)
+        g = stored(g, storage, ref)
+    return stored(collide(g, cfg.tau, cfg.gx, cfg.gy), storage, ref)
 
 
 def run(f: np.ndarray, cfg, n: int) -> np.ndarray:

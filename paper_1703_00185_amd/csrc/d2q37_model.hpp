@@ -66,6 +66,7 @@ D2Q37_HD constexpr int opp_of(int l) {
   return SHELL_START[s] + SHELL_START[s + 1] - 1 - l;
 }
 D2Q37_HD constexpr double weight_of(int l) { return W_SHELL[shell_of(l)]; }
+D2Q37_HD constexpr double inv_weight_of(int l) { return 1.0 / W_SHELL[shell_of(l)]; }
 
 // Wall factor K_l(T) (zero-velocity equilibrium per unit density at
 // temperature T).  Evaluated with no contraction in this exact order:

@@ -35,17 +35,53 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
   return xcd * q + (xcd < r ? xcd : r) + idx;
 }
 
-// Population storage: binary64, or binary32 widened exactly on load and
-// rounded to nearest on store.  All arithmetic is binary64 either way.
-// Offsets are in bytes from a wavefront-uniform base.
+// Raw element access at a byte offset from a wavefront-uniform base.
 template <class S>
-__device__ __forceinline__ double ld(const S* base, unsigned byte_off) {
-  return static_cast<double>(*reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + byte_off));
+__device__ __forceinline__ S ld(const S* base, unsigned byte_off) {
+  return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + byte_off);
 }
 template <class S>
-__device__ __forceinline__ void st(S* base, unsigned byte_off, double v) {
-  *reinterpret_cast<S*>(reinterpret_cast<char*>(base) + byte_off) = static_cast<S>(v);
+__device__ __forceinline__ void st(S* base, unsigned byte_off, S v) {
+  *reinterpret_cast<S*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
+
+// Population storage codecs.  Arithmetic is binary64 for every storage;
+// a codec turns the stored element of population l at row y into the
+// binary64 population and back.
+//  * binary64: identity.
+//  * binary32: exact widening; rounding to nearest on store.
+//  * binary16 deviation: the element is d = (f - c) / c with the reference
+//    c = w_l rho_ref(y) (a per-row reference density); stored as
+//    d = f16(f32((f - c) * (w_l^-1 * rho_ref(y)^-1))) and read back as
+//    c (1 + d).  1 + d is exact in binary64, so decoding rounds once.
+struct CodecF64 {
+  using S = double;
+  const double* ref;
+  const double* inv_ref;
+  __device__ double dec(S v, int, int) const { return v; }
+  __device__ S enc(double f, int, int) const { return f; }
+};
+struct CodecF32 {
+  using S = float;
+  const double* ref;
+  const double* inv_ref;
+  __device__ double dec(S v, int, int) const { return static_cast<double>(v); }
+  __device__ S enc(double f, int, int) const { return static_cast<float>(f); }
+};
+struct CodecF16Dev {
+  using S = _Float16;
+  const double* ref;
+  const double* inv_ref;
+  __device__ double dec(S v, int l, int y) const {
+    const double c = weight_of(l) * ref[y];
+    return c * (1.0 + static_cast<double>(static_cast<float>(v)));
+  }
+  __device__ S enc(double f, int l, int y) const {
+    const double c = weight_of(l) * ref[y];
+    const double q = (f - c) * (inv_weight_of(l) * inv_ref[y]);
+    return static_cast<_Float16>(static_cast<float>(q));
+  }
+};
 
 // acc + k * v for a small integer k known after unrolling.
 __device__ __forceinline__ double add_scaled(double acc, int k, double v) {
@@ -197,22 +233,25 @@ __device__ __forceinline__ bool interior_wave(const Geometry& g, int ywave) {
 // x - e_lx < 0 or >= Lx read the halo columns filled by pbc.  Interior
 // form: the per-population offset is uniform and the per-lane byte offset
 // is shared by all 37 loads.
-template <class S>
-__device__ __forceinline__ void gather_interior(const Geometry& g, const S* __restrict__ src,
-                                                int x, int y, double (&f)[NPOP]) {
+template <class C>
+__device__ __forceinline__ void gather_interior(const Geometry& g, const C& cd,
+                                                const typename C::S* __restrict__ src, int x, int y,
+                                                double (&f)[NPOP]) {
+  using S = typename C::S;
   const unsigned off = static_cast<unsigned>((x + HALO) * g.ny + y) * static_cast<unsigned>(sizeof(S));
 #pragma unroll
   for (int l = 0; l < NPOP; ++l) {
     const S* base = src + (static_cast<long long>(l) * g.plane - (EX[l] * g.ny + EY[l]));
-    f[l] = ld(base, off);
+    f[l] = cd.dec(ld(base, off), l, y - EY[l]);
   }
 }
 
 // General form, for wavefronts touching the walls: a source row beyond a
 // wall is replaced by the opposite population of the same site.
-template <class S>
-__device__ __forceinline__ void gather_wall(const Geometry& g, const S* __restrict__ src,
-                                            int x, int y, double (&f)[NPOP]) {
+template <class C>
+__device__ __forceinline__ void gather_wall(const Geometry& g, const C& cd,
+                                            const typename C::S* __restrict__ src, int x, int y,
+                                            double (&f)[NPOP]) {
   const int X = x + HALO;
 #pragma unroll
   for (int l = 0; l < NPOP; ++l) {
@@ -221,24 +260,27 @@ __device__ __forceinline__ void gather_wall(const Geometry& g, const S* __restri
     const long long idx = inside
         ? static_cast<long long>(l) * g.plane + static_cast<long long>(X - EX[l]) * g.ny + ys
         : static_cast<long long>(opp_of(l)) * g.plane + static_cast<long long>(X) * g.ny + y;
-    f[l] = static_cast<double>(src[idx]);
+    f[l] = cd.dec(src[idx], l, inside ? ys : y);  // opp(l) shares w_l
   }
 }
 
-template <class S>
-__device__ __forceinline__ void load_site(const Geometry& g, const S* __restrict__ src,
-                                          int x, int y, double (&f)[NPOP]) {
+template <class C>
+__device__ __forceinline__ void load_site(const Geometry& g, const C& cd,
+                                          const typename C::S* __restrict__ src, int x, int y,
+                                          double (&f)[NPOP]) {
+  using S = typename C::S;
   const unsigned off = static_cast<unsigned>((x + HALO) * g.ny + y) * static_cast<unsigned>(sizeof(S));
 #pragma unroll
-  for (int l = 0; l < NPOP; ++l) f[l] = ld(src + static_cast<long long>(l) * g.plane, off);
+  for (int l = 0; l < NPOP; ++l) f[l] = cd.dec(ld(src + static_cast<long long>(l) * g.plane, off), l, y);
 }
 
-template <class S>
-__device__ __forceinline__ void store_site(const Geometry& g, S* __restrict__ dst,
+template <class C>
+__device__ __forceinline__ void store_site(const Geometry& g, const C& cd, typename C::S* __restrict__ dst,
                                            int x, int y, const double (&f)[NPOP]) {
+  using S = typename C::S;
   const unsigned off = static_cast<unsigned>((x + HALO) * g.ny + y) * static_cast<unsigned>(sizeof(S));
 #pragma unroll
-  for (int l = 0; l < NPOP; ++l) st(dst + static_cast<long long>(l) * g.plane, off, f[l]);
+  for (int l = 0; l < NPOP; ++l) st(dst + static_cast<long long>(l) * g.plane, off, cd.enc(f[l], l, y));
 }
 
 // ---------------------------------------------------------------------------
@@ -291,23 +333,25 @@ __global__ void __launch_bounds__(256) pbc_kernel(S* __restrict__ f, Geometry g)
 }
 
 // propagate (Sec. 4): pull gather into the other lattice copy.
-template <class S, int BLOCK>
-__global__ void __launch_bounds__(BLOCK) propagate_kernel(const S* __restrict__ src,
-                                                          S* __restrict__ dst, Geometry g) {
+template <class C, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) propagate_kernel(const typename C::S* __restrict__ src,
+                                                          typename C::S* __restrict__ dst, Geometry g) {
+  const C cd{g.ref, g.inv_ref};
   int x, y, ywave;
   lane_site<BLOCK>(g, x, y, ywave);
   double f[NPOP];
   if (interior_wave(g, ywave)) {
-    gather_interior(g, src, x, y, f);
+    gather_interior(g, cd, src, x, y, f);
   } else {
-    gather_wall(g, src, x, y < g.ly ? y : g.ly - 1, f);
+    gather_wall(g, cd, src, x, y < g.ly ? y : g.ly - 1, f);
   }
-  if (y < g.ly) store_site(g, dst, x, y, f);
+  if (y < g.ly) store_site(g, cd, dst, x, y, f);
 }
 
 // bc (Sec. 4): thermal walls, in place, on the 3 bottom and 3 top rows.
-template <class S>
-__global__ void __launch_bounds__(256) bc_kernel(S* __restrict__ f, Geometry g, WallParams w) {
+template <class C>
+__global__ void __launch_bounds__(256) bc_kernel(typename C::S* __restrict__ f, Geometry g, WallParams w) {
+  const C cd{g.ref, g.inv_ref};
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= g.lx * 2 * WALL_ROWS) return;
   const int x = t / (2 * WALL_ROWS);
@@ -315,58 +359,61 @@ __global__ void __launch_bounds__(256) bc_kernel(S* __restrict__ f, Geometry g, 
   const bool bottom = r < WALL_ROWS;
   const int y = bottom ? r : g.ly - 2 * WALL_ROWS + r;
   double v[NPOP];
-  load_site(g, f, x, y, v);
+  load_site(g, cd, f, x, y, v);
   thermalise(v, bottom, w);
-  store_site(g, f, x, y, v);
+  store_site(g, cd, f, x, y, v);
 }
 
 // collide (Sec. 4): site-local collision into the other lattice copy.
-template <class S, int BLOCK>
-__global__ void __launch_bounds__(BLOCK) collide_kernel(const S* __restrict__ src,
-                                                        S* __restrict__ dst, Geometry g,
+template <class C, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) collide_kernel(const typename C::S* __restrict__ src,
+                                                        typename C::S* __restrict__ dst, Geometry g,
                                                         CollideParams c) {
+  const C cd{g.ref, g.inv_ref};
   int x, y, ywave;
   lane_site<BLOCK>(g, x, y, ywave);
   if (y >= g.ly) return;
   double f[NPOP];
-  load_site(g, src, x, y, f);
+  load_site(g, cd, src, x, y, f);
   collide_site(f, c);
-  store_site(g, dst, x, y, f);
+  store_site(g, cd, dst, x, y, f);
 }
 
 // propagate + bc + collide in registers: one read and one write of every
 // population per step (the fusion the paper applies in Sec. 5, here on
 // every row, walls included, since bc is site-local).
-template <class S, int BLOCK>
-__global__ void __launch_bounds__(BLOCK) fused_kernel(const S* __restrict__ src,
-                                                      S* __restrict__ dst, Geometry g,
+template <class C, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) fused_kernel(const typename C::S* __restrict__ src,
+                                                      typename C::S* __restrict__ dst, Geometry g,
                                                       CollideParams c, WallParams w) {
+  const C cd{g.ref, g.inv_ref};
   int x, y, ywave;
   lane_site<BLOCK>(g, x, y, ywave);
   double f[NPOP];
   if (interior_wave(g, ywave)) {
-    gather_interior(g, src, x, y, f);
+    gather_interior(g, cd, src, x, y, f);
   } else {
     const int yc = y < g.ly ? y : g.ly - 1;
-    gather_wall(g, src, x, yc, f);
+    gather_wall(g, cd, src, x, yc, f);
     if (yc < WALL_ROWS || yc >= g.ly - WALL_ROWS) thermalise(f, yc < WALL_ROWS, w);
   }
   collide_site(f, c);
-  if (y < g.ly) store_site(g, dst, x, y, f);
+  if (y < g.ly) store_site(g, cd, dst, x, y, f);
 }
 
 // Per-site rho, ux, uy, T into out[4][lx][ly] (Sec. 2 moment definitions;
 // D rho T = sum |c|^2 f - rho |u|^2).
-template <class S>
-__global__ void __launch_bounds__(256) moments_kernel(const S* __restrict__ src,
+template <class C>
+__global__ void __launch_bounds__(256) moments_kernel(const typename C::S* __restrict__ src,
                                                       double* __restrict__ out, Geometry g) {
+  const C cd{g.ref, g.inv_ref};
   const long long n = static_cast<long long>(g.lx) * g.ly;
   const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
   if (i >= n) return;
   const int x = static_cast<int>(i / g.ly);
   const int y = static_cast<int>(i - static_cast<long long>(x) * g.ly);
   double f[NPOP];
-  load_site(g, src, x, y, f);
+  load_site(g, cd, src, x, y, f);
   const MomentSums m = moment_sums(f);
   const double inv_rho = 1.0 / m.rho;
   const double ux = R * m.jx * inv_rho;
@@ -395,9 +442,10 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
 
 // Conservation sums, pass 1: each work-group walks a fixed strided set of
 // sites and writes its 5 partial sums.
-template <class S>
+template <class C>
 __global__ void __launch_bounds__(CONS_THREADS) conservation_partial_kernel(
-    const S* __restrict__ src, Geometry g, double* __restrict__ partials) {
+    const typename C::S* __restrict__ src, Geometry g, double* __restrict__ partials) {
+  const C cd{g.ref, g.inv_ref};
   __shared__ double lds[CONS_THREADS / WAVE];
   const long long n = static_cast<long long>(g.lx) * g.ly;
   double acc[CONS_FIELDS] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -406,7 +454,7 @@ __global__ void __launch_bounds__(CONS_THREADS) conservation_partial_kernel(
     const int x = static_cast<int>(i / g.ly);
     const int y = static_cast<int>(i - static_cast<long long>(x) * g.ly);
     double f[NPOP];
-    load_site(g, src, x, y, f);
+    load_site(g, cd, src, x, y, f);
     int bad = 0;
 #pragma unroll
     for (int l = 0; l < NPOP; ++l) bad += isfinite(f[l]) ? 0 : 1;
@@ -439,16 +487,17 @@ __global__ void __launch_bounds__(CONS_THREADS) conservation_final_kernel(
 
 // Gather the populations of n listed sites (coordinates checked on the
 // host): out[l * n + i] = f_l(xy[2i], xy[2i+1]).
-template <class S>
-__global__ void __launch_bounds__(256) get_sites_kernel(const S* __restrict__ f, Geometry g,
+template <class C>
+__global__ void __launch_bounds__(256) get_sites_kernel(const typename C::S* __restrict__ f, Geometry g,
                                                         const int* __restrict__ xy, int n,
                                                         double* __restrict__ out) {
+  const C cd{g.ref, g.inv_ref};
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const int x = xy[2 * i];
   const int y = xy[2 * i + 1];
   double v[NPOP];
-  load_site(g, f, x, y, v);
+  load_site(g, cd, f, x, y, v);
 #pragma unroll
   for (int l = 0; l < NPOP; ++l) out[static_cast<long long>(l) * n + i] = v[l];
 }
@@ -458,12 +507,27 @@ __device__ __forceinline__ double log_cosh(double z) {
   return (a + log1p(exp(-2.0 * a))) - 0.6931471805599453094172321;
 }
 
-// Rayleigh-Taylor initial state: tanh temperature interface perturbed by
-// Fourier modes, pressure in hydrostatic balance d ln p / dy = r gy / T
-// (closed-form integral from the interface, where p = 1), rho = p / T,
-// populations at the zero-velocity equilibrium rho K_l(T).
-template <class S>
-__global__ void __launch_bounds__(256) init_rt_kernel(S* __restrict__ f, Geometry g, RtParams p) {
+// Rayleigh-Taylor fields at row y of a column whose interface is displaced
+// by h: tanh temperature interface, pressure in hydrostatic balance
+// d ln p / dy = r gy / T (closed-form integral from the interface, where
+// p = 1), rho = p / T.
+__device__ __forceinline__ void rt_fields(const RtParams& p, int y, double h, double& rho,
+                                          double& temp) {
+  const double z = ((static_cast<double>(y) - p.y_center) - h) / p.width;
+  temp = p.tm - p.a * tanh(z);
+  const double z0 = atanh(p.a / p.tm);
+  const double integral = p.width * (p.tm * z + p.a * (log_cosh(z - z0) - log_cosh(-z0))) /
+                          (p.tm * p.tm - p.a * p.a);
+  rho = exp(R * p.gy * integral) / temp;
+}
+
+// Rayleigh-Taylor initial state: interface displaced by the Fourier modes
+// h(x), populations at the zero-velocity equilibrium rho K_l(T).
+template <class C>
+__global__ void __launch_bounds__(256) init_rt_kernel(typename C::S* __restrict__ f, Geometry g,
+                                                      RtParams p) {
+  using S = typename C::S;
+  const C cd{g.ref, g.inv_ref};
   const long long n = static_cast<long long>(g.lx) * g.ly;
   const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
   if (i >= n) return;
@@ -474,20 +538,56 @@ __global__ void __launch_bounds__(256) init_rt_kernel(S* __restrict__ f, Geometr
   for (int k = 0; k < p.n_modes; ++k)
     h = h + p.amp[k] * cos(two_pi * static_cast<double>(k + 1) * static_cast<double>(x) /
                                static_cast<double>(g.lx) + p.phase[k]);
-  const double z = ((static_cast<double>(y) - p.y_center) - h) / p.width;
-  const double temp = p.tm - p.a * tanh(z);
-  const double z0 = atanh(p.a / p.tm);
-  const double integral = p.width * (p.tm * z + p.a * (log_cosh(z - z0) - log_cosh(-z0))) /
-                          (p.tm * p.tm - p.a * p.a);
-  const double rho = exp(R * p.gy * integral) / temp;
+  double rho, temp;
+  rt_fields(p, y, h, rho, temp);
   const double th = temp - 1.0;
   const unsigned off = static_cast<unsigned>((x + HALO) * g.ny + y) * static_cast<unsigned>(sizeof(S));
 #pragma unroll
   for (int l = 0; l < NPOP; ++l) {
-    const double C = R2 * static_cast<double>(EX[l] * EX[l] + EY[l] * EY[l]);
-    const double k = weight_of(l) * ((1.0 + th * (C - 2.0) / 2.0) + th * th * (C * C - 8.0 * C + 8.0) / 8.0);
-    st(f + static_cast<long long>(l) * g.plane, off, rho * k);
+    const double C2 = R2 * static_cast<double>(EX[l] * EX[l] + EY[l] * EY[l]);
+    const double k = weight_of(l) * ((1.0 + th * (C2 - 2.0) / 2.0) + th * th * (C2 * C2 - 8.0 * C2 + 8.0) / 8.0);
+    st(f + static_cast<long long>(l) * g.plane, off, cd.enc(rho * k, l, y));
   }
+}
+
+// Per-row reference density of the deviation storage: the density of the
+// Rayleigh-Taylor state with a flat interface, and its reciprocal.
+__global__ void __launch_bounds__(256) rt_reference_kernel(double* __restrict__ ref,
+                                                           double* __restrict__ inv_ref, int ly,
+                                                           RtParams p) {
+  const int y = blockIdx.x * 256 + threadIdx.x;
+  if (y >= ly) return;
+  double rho, temp;
+  rt_fields(p, y, 0.0, rho, temp);
+  ref[y] = rho;
+  inv_ref[y] = 1.0 / rho;
+}
+
+// Host-array transfers through the codec: one population plane at a time
+// between binary64 values [x][y] and the stored plane.
+template <class C>
+__global__ void __launch_bounds__(256) encode_plane_kernel(const double* __restrict__ in,
+                                                           typename C::S* __restrict__ plane,
+                                                           Geometry g, int l) {
+  const C cd{g.ref, g.inv_ref};
+  const long long n = static_cast<long long>(g.lx) * g.ly;
+  const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int x = static_cast<int>(i / g.ly);
+  const int y = static_cast<int>(i - static_cast<long long>(x) * g.ly);
+  plane[static_cast<long long>(x + HALO) * g.ny + y] = cd.enc(in[i], l, y);
+}
+
+template <class C>
+__global__ void __launch_bounds__(256) decode_plane_kernel(const typename C::S* __restrict__ plane,
+                                                           double* __restrict__ out, Geometry g, int l) {
+  const C cd{g.ref, g.inv_ref};
+  const long long n = static_cast<long long>(g.lx) * g.ly;
+  const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int x = static_cast<int>(i / g.ly);
+  const int y = static_cast<int>(i - static_cast<long long>(x) * g.ly);
+  out[i] = cd.dec(plane[static_cast<long long>(x + HALO) * g.ny + y], l, y);
 }
 
 // ---------------------------------------------------------------------------
@@ -517,14 +617,15 @@ __global__ void __launch_bounds__(PROBE_THREADS) probe_shift_kernel(const double
 
 }  // namespace
 
-// Dispatch on storage type (S) and work-group size (BS).
-#define D2Q37_DISPATCH(G, ...)                                        \
-  switch ((G).storage) {                                               \
-    case STORAGE_F64: { using S = double; D2Q37_BLOCKS(G, __VA_ARGS__); break; } \
-    case STORAGE_F32: { using S = float; D2Q37_BLOCKS(G, __VA_ARGS__); break; }  \
-    default: return hipErrorInvalidValue;                              \
+// Dispatch on the storage codec (C, element type S) and work-group size (BS).
+#define D2Q37_DISPATCH(G, ...)                                                         \
+  switch ((G).storage) {                                                               \
+    case STORAGE_F64: { using C = CodecF64; using S = C::S; D2Q37_BLOCKS(G, __VA_ARGS__); break; }  \
+    case STORAGE_F32: { using C = CodecF32; using S = C::S; D2Q37_BLOCKS(G, __VA_ARGS__); break; }  \
+    case STORAGE_F16DEV: { using C = CodecF16Dev; using S = C::S; D2Q37_BLOCKS(G, __VA_ARGS__); break; } \
+    default: return hipErrorInvalidValue;                                              \
   }
-#define D2Q37_BLOCKS(G, ...)                               \
+#define D2Q37_BLOCKS(G, ...)                                \
   switch ((G).block) {                                      \
     case 64: { constexpr int BS = 64; __VA_ARGS__; break; }        \
     case 128: { constexpr int BS = 128; __VA_ARGS__; break; }      \
@@ -533,11 +634,12 @@ __global__ void __launch_bounds__(PROBE_THREADS) probe_shift_kernel(const double
     case 1024: { constexpr int BS = 1024; __VA_ARGS__; break; }    \
     default: return hipErrorInvalidValue;                   \
   }
-#define D2Q37_STORAGE(G, ...)                                         \
-  switch ((G).storage) {                                               \
-    case STORAGE_F64: { using S = double; __VA_ARGS__; break; }               \
-    case STORAGE_F32: { using S = float; __VA_ARGS__; break; }                \
-    default: return hipErrorInvalidValue;                              \
+#define D2Q37_STORAGE(G, ...)                                                          \
+  switch ((G).storage) {                                                               \
+    case STORAGE_F64: { using C = CodecF64; using S = C::S; __VA_ARGS__; break; }      \
+    case STORAGE_F32: { using C = CodecF32; using S = C::S; __VA_ARGS__; break; }      \
+    case STORAGE_F16DEV: { using C = CodecF16Dev; using S = C::S; __VA_ARGS__; break; } \
+    default: return hipErrorInvalidValue;                                              \
   }
 
 hipError_t launch_pbc(const Geometry& g, void* f, hipStream_t s) {
@@ -549,7 +651,7 @@ hipError_t launch_pbc(const Geometry& g, void* f, hipStream_t s) {
 
 hipError_t launch_propagate(const Geometry& g, const void* src, void* dst, hipStream_t s) {
   (void)hipGetLastError();
-  D2Q37_DISPATCH(g, hipLaunchKernelGGL((propagate_kernel<S, BS>), dim3(g.lx * g.ny_blocks), dim3(BS),
+  D2Q37_DISPATCH(g, hipLaunchKernelGGL((propagate_kernel<C, BS>), dim3(g.lx * g.ny_blocks), dim3(BS),
                                        0, s, static_cast<const S*>(src), static_cast<S*>(dst), g));
   return hipGetLastError();
 }
@@ -557,7 +659,7 @@ hipError_t launch_propagate(const Geometry& g, const void* src, void* dst, hipSt
 hipError_t launch_bc(const Geometry& g, void* f, const WallParams& w, hipStream_t s) {
   const int n = g.lx * 2 * WALL_ROWS;
   (void)hipGetLastError();
-  D2Q37_STORAGE(g, hipLaunchKernelGGL(bc_kernel<S>, dim3((n + 255) / 256), dim3(256), 0, s,
+  D2Q37_STORAGE(g, hipLaunchKernelGGL(bc_kernel<C>, dim3((n + 255) / 256), dim3(256), 0, s,
                                       static_cast<S*>(f), g, w));
   return hipGetLastError();
 }
@@ -565,7 +667,7 @@ hipError_t launch_bc(const Geometry& g, void* f, const WallParams& w, hipStream_
 hipError_t launch_collide(const Geometry& g, const void* src, void* dst, const CollideParams& c,
                           hipStream_t s) {
   (void)hipGetLastError();
-  D2Q37_DISPATCH(g, hipLaunchKernelGGL((collide_kernel<S, BS>), dim3(g.lx * g.ny_blocks), dim3(BS),
+  D2Q37_DISPATCH(g, hipLaunchKernelGGL((collide_kernel<C, BS>), dim3(g.lx * g.ny_blocks), dim3(BS),
                                        0, s, static_cast<const S*>(src), static_cast<S*>(dst), g, c));
   return hipGetLastError();
 }
@@ -573,7 +675,7 @@ hipError_t launch_collide(const Geometry& g, const void* src, void* dst, const C
 hipError_t launch_fused(const Geometry& g, const void* src, void* dst, const CollideParams& c,
                         const WallParams& w, hipStream_t s) {
   (void)hipGetLastError();
-  D2Q37_DISPATCH(g, hipLaunchKernelGGL((fused_kernel<S, BS>), dim3(g.lx * g.ny_blocks), dim3(BS), 0,
+  D2Q37_DISPATCH(g, hipLaunchKernelGGL((fused_kernel<C, BS>), dim3(g.lx * g.ny_blocks), dim3(BS), 0,
                                        s, static_cast<const S*>(src), static_cast<S*>(dst), g, c, w));
   return hipGetLastError();
 }
@@ -581,7 +683,7 @@ hipError_t launch_fused(const Geometry& g, const void* src, void* dst, const Col
 hipError_t launch_moments(const Geometry& g, const void* f, double* out, hipStream_t s) {
   const long long n = static_cast<long long>(g.lx) * g.ly;
   (void)hipGetLastError();
-  D2Q37_STORAGE(g, hipLaunchKernelGGL(moments_kernel<S>, dim3(static_cast<unsigned>((n + 255) / 256)),
+  D2Q37_STORAGE(g, hipLaunchKernelGGL(moments_kernel<C>, dim3(static_cast<unsigned>((n + 255) / 256)),
                                       dim3(256), 0, s, static_cast<const S*>(f), out, g));
   return hipGetLastError();
 }
@@ -589,7 +691,7 @@ hipError_t launch_moments(const Geometry& g, const void* f, double* out, hipStre
 hipError_t launch_conservation(const Geometry& g, const void* f, double* partials, double* result,
                                hipStream_t s) {
   (void)hipGetLastError();
-  D2Q37_STORAGE(g, hipLaunchKernelGGL(conservation_partial_kernel<S>, dim3(CONS_BLOCKS),
+  D2Q37_STORAGE(g, hipLaunchKernelGGL(conservation_partial_kernel<C>, dim3(CONS_BLOCKS),
                                       dim3(CONS_THREADS), 0, s, static_cast<const S*>(f), g, partials));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -601,7 +703,7 @@ hipError_t launch_conservation(const Geometry& g, const void* f, double* partial
 hipError_t launch_get_sites(const Geometry& g, const void* f, const int* xy, int n, double* out,
                             hipStream_t s) {
   (void)hipGetLastError();
-  D2Q37_STORAGE(g, hipLaunchKernelGGL(get_sites_kernel<S>, dim3((n + 255) / 256), dim3(256), 0, s,
+  D2Q37_STORAGE(g, hipLaunchKernelGGL(get_sites_kernel<C>, dim3((n + 255) / 256), dim3(256), 0, s,
                                       static_cast<const S*>(f), g, xy, n, out));
   return hipGetLastError();
 }
@@ -625,10 +727,33 @@ hipError_t launch_probe(int mode, const void* src, void* dst, size_t n16, int sh
   return hipGetLastError();
 }
 
+hipError_t launch_rt_reference(const Geometry& g, double* ref, double* inv_ref, const RtParams& p,
+                               hipStream_t s) {
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(rt_reference_kernel, dim3((g.ly + 255) / 256), dim3(256), 0, s, ref, inv_ref, g.ly, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_plane(const Geometry& g, const double* in, void* f, int l, hipStream_t s) {
+  const long long n = static_cast<long long>(g.lx) * g.ly;
+  (void)hipGetLastError();
+  D2Q37_STORAGE(g, hipLaunchKernelGGL(encode_plane_kernel<C>, dim3(static_cast<unsigned>((n + 255) / 256)),
+                                      dim3(256), 0, s, in, static_cast<S*>(f) + l * g.plane, g, l));
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_plane(const Geometry& g, const void* f, double* out, int l, hipStream_t s) {
+  const long long n = static_cast<long long>(g.lx) * g.ly;
+  (void)hipGetLastError();
+  D2Q37_STORAGE(g, hipLaunchKernelGGL(decode_plane_kernel<C>, dim3(static_cast<unsigned>((n + 255) / 256)),
+                                      dim3(256), 0, s, static_cast<const S*>(f) + l * g.plane, out, g, l));
+  return hipGetLastError();
+}
+
 hipError_t launch_init_rt(const Geometry& g, void* f, const RtParams& p, hipStream_t s) {
   const long long n = static_cast<long long>(g.lx) * g.ly;
   (void)hipGetLastError();
-  D2Q37_STORAGE(g, hipLaunchKernelGGL(init_rt_kernel<S>, dim3(static_cast<unsigned>((n + 255) / 256)),
+  D2Q37_STORAGE(g, hipLaunchKernelGGL(init_rt_kernel<C>, dim3(static_cast<unsigned>((n + 255) / 256)),
                                       dim3(256), 0, s, static_cast<S*>(f), g, p));
   return hipGetLastError();
 }

@@ -13,7 +13,7 @@ namespace d2q37 {
 // rows >= ly being padding that is never read.  Element (l, X, y) sits at
 // l * plane + X * ny + y.
 // Population storage types.
-enum Storage : int { STORAGE_F64 = 0, STORAGE_F32 = 1 };
+enum Storage : int { STORAGE_F64 = 0, STORAGE_F32 = 1, STORAGE_F16DEV = 2 };
 
 struct Geometry {
   int lx, ly;
@@ -22,6 +22,8 @@ struct Geometry {
   int block;         // work-group size of the lattice kernels
   int ny_blocks;     // ceil(ly / block)
   long long plane;   // population plane stride, elements
+  const double* ref;      // per-row reference density (deviation storage)
+  const double* inv_ref;  // its reciprocal
 };
 
 // Scalars of the collision (Eqs. 4-6): omega = 1/tau, the shift tau*g of
@@ -69,6 +71,10 @@ hipError_t launch_conservation(const Geometry& g, const void* f, double* partial
 hipError_t launch_get_sites(const Geometry& g, const void* f, const int* xy, int n, double* out,
                             hipStream_t s);
 hipError_t launch_init_rt(const Geometry& g, void* f, const RtParams& p, hipStream_t s);
+hipError_t launch_rt_reference(const Geometry& g, double* ref, double* inv_ref, const RtParams& p,
+                               hipStream_t s);
+hipError_t launch_encode_plane(const Geometry& g, const double* in, void* f, int l, hipStream_t s);
+hipError_t launch_decode_plane(const Geometry& g, const void* f, double* out, int l, hipStream_t s);
 
 // Copy probes (aligned copy, misaligned read / aligned write, aligned read /
 // misaligned write); n16 = bytes / 16, shift in doubles.

@@ -24,6 +24,7 @@ struct lbm_handle {
   hipStream_t stream = nullptr;
   int device = 0;
   bool ready = false;
+  bool has_ref = false;  // deviation storage: reference density set
   CollideParams cp{};
   WallParams wp{};
   std::string err;
@@ -61,11 +62,15 @@ constexpr long long kMaxPlaneElems = (1LL << 29);  // byte offsets inside a plan
 
 long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
 
-int elem_bytes(const Geometry& g) { return g.storage == STORAGE_F32 ? 4 : 8; }
+int elem_bytes(const Geometry& g) {
+  return g.storage == STORAGE_F32 ? 4 : g.storage == STORAGE_F16DEV ? 2 : 8;
+}
 
 struct Layout {
   Geometry geo;
   size_t buf_bytes;
+  size_t ref_bytes;  // deviation storage: rho_ref[ly] and 1/rho_ref[ly], each 256-aligned
+  size_t total() const { return 2 * buf_bytes + 2 * ref_bytes; }
 };
 
 // Validate cfg and derive the layout; returns LBM_OK or LBM_EINVAL with *why.
@@ -78,8 +83,8 @@ int make_layout(const lbm_config* c, Layout* out, std::string* why) {
   if (!std::isfinite(c->t_bottom) || !(c->t_bottom > 0.0) || !std::isfinite(c->t_top) ||
       !(c->t_top > 0.0))
     return *why = "wall temperatures must be finite and > 0", LBM_EINVAL;
-  if (c->storage != LBM_FP64 && c->storage != LBM_FP32)
-    return *why = "storage must be LBM_FP64 or LBM_FP32", LBM_EINVAL;
+  if (c->storage != LBM_FP64 && c->storage != LBM_FP32 && c->storage != LBM_FP16DEV)
+    return *why = "storage must be LBM_FP64, LBM_FP32 or LBM_FP16DEV", LBM_EINVAL;
   if (c->path != LBM_PATH_SEPARATE && c->path != LBM_PATH_FUSED)
     return *why = "path must be LBM_PATH_SEPARATE or LBM_PATH_FUSED", LBM_EINVAL;
   const int block = c->block == 0 ? 256 : c->block;
@@ -91,7 +96,8 @@ int make_layout(const lbm_config* c, Layout* out, std::string* why) {
   Geometry g{};
   g.lx = c->lx;
   g.ly = c->ly;
-  g.storage = c->storage == LBM_FP32 ? STORAGE_F32 : STORAGE_F64;
+  g.storage = c->storage == LBM_FP32 ? STORAGE_F32
+              : c->storage == LBM_FP16DEV ? STORAGE_F16DEV : STORAGE_F64;
   g.block = block;
   const long long ny = round_up(c->ly, 64) + (c->ny_pad > 0 ? c->ny_pad : 0);
   const long long nx = static_cast<long long>(c->lx) + 2 * HALO;
@@ -105,6 +111,10 @@ int make_layout(const lbm_config* c, Layout* out, std::string* why) {
   out->geo = g;
   out->buf_bytes =
       static_cast<size_t>(round_up(static_cast<long long>(NPOP) * g.plane * elem_bytes(g), 256));
+  out->ref_bytes = g.storage == STORAGE_F16DEV ? static_cast<size_t>(round_up(8LL * c->ly, 256)) : 0;
+  // host transfers stage one plane of binary64 values in the idle copy
+  if (static_cast<size_t>(8) * c->lx * c->ly > out->buf_bytes)
+    return *why = "internal: staging does not fit", LBM_EINVAL;
   return LBM_OK;
 }
 
@@ -210,7 +220,7 @@ size_t lbm_required_bytes(const lbm_config* cfg) {
     fail(nullptr, LBM_EINVAL, why);
     return 0;
   }
-  return 2 * L.buf_bytes;
+  return L.total();
 }
 
 int lbm_create(const lbm_config* cfg, void* dev_mem, size_t dev_bytes, void* stream,
@@ -223,9 +233,9 @@ int lbm_create(const lbm_config* cfg, void* dev_mem, size_t dev_bytes, void* str
   if (!dev_mem) return fail(nullptr, LBM_EINVAL, "dev_mem is NULL");
   if (reinterpret_cast<uintptr_t>(dev_mem) % 256 != 0)
     return fail(nullptr, LBM_ENOMEM, "dev_mem must be 256-byte aligned");
-  if (dev_bytes < 2 * L.buf_bytes)
+  if (dev_bytes < L.total())
     return fail(nullptr, LBM_ENOMEM,
-                "dev_bytes " + std::to_string(dev_bytes) + " < required " + std::to_string(2 * L.buf_bytes));
+                "dev_bytes " + std::to_string(dev_bytes) + " < required " + std::to_string(L.total()));
   hipPointerAttribute_t attr;
   hipError_t e = hipPointerGetAttributes(&attr, dev_mem);
   if (e != hipSuccess) {
@@ -242,6 +252,11 @@ int lbm_create(const lbm_config* cfg, void* dev_mem, size_t dev_bytes, void* str
   h->buf_bytes = L.buf_bytes;
   h->buf[0] = static_cast<char*>(dev_mem);
   h->buf[1] = static_cast<char*>(dev_mem) + L.buf_bytes;
+  if (L.ref_bytes) {
+    h->geo.ref = reinterpret_cast<const double*>(static_cast<char*>(dev_mem) + 2 * L.buf_bytes);
+    h->geo.inv_ref = reinterpret_cast<const double*>(static_cast<char*>(dev_mem) + 2 * L.buf_bytes +
+                                                     L.ref_bytes);
+  }
   h->stream = static_cast<hipStream_t>(stream);
   h->device = attr.device;
   const double tau = cfg->tau;
@@ -286,6 +301,11 @@ int lbm_init_rt(lbm_handle* h, const lbm_rt_params* rt) {
     p.phase[k] = rt->phase[k];
   }
   DeviceGuard dg(h->device);
+  if (h->geo.storage == STORAGE_F16DEV) {
+    LBM_HIP(h, launch_rt_reference(h->geo, const_cast<double*>(h->geo.ref),
+                                   const_cast<double*>(h->geo.inv_ref), p, h->stream));
+    h->has_ref = true;
+  }
   LBM_HIP(h, launch_init_rt(h->geo, current(h), p, h->stream));
   h->ready = true;
   return LBM_OK;
@@ -356,18 +376,12 @@ int lbm_get_populations(lbm_handle* h, double* host) {
   if (!h->ready) return fail(h, LBM_ESTATE, "lattice not initialised");
   DeviceGuard dg(h->device);
   const Geometry& g = h->geo;
-  const size_t eb = elem_bytes(g);
   const size_t n = static_cast<size_t>(g.lx) * g.ly;
-  std::vector<float> tmp(g.storage == STORAGE_F32 ? n : 0);
+  double* stage = scratch(h);
   for (int l = 0; l < NPOP; ++l) {
-    double* dst = host + static_cast<size_t>(l) * n;
-    void* stage = g.storage == STORAGE_F32 ? static_cast<void*>(tmp.data()) : static_cast<void*>(dst);
-    LBM_HIP(h, hipMemcpy2DAsync(stage, g.ly * eb, current(h) + plane_col0(g, l), g.ny * eb, g.ly * eb,
-                                g.lx, hipMemcpyDeviceToHost, h->stream));
-    if (g.storage == STORAGE_F32) {
-      LBM_HIP(h, hipStreamSynchronize(h->stream));
-      for (size_t i = 0; i < n; ++i) dst[i] = static_cast<double>(tmp[i]);  // exact widening
-    }
+    LBM_HIP(h, launch_decode_plane(g, current(h), stage, l, h->stream));
+    LBM_HIP(h, hipMemcpyAsync(host + static_cast<size_t>(l) * n, stage, n * sizeof(double),
+                              hipMemcpyDeviceToHost, h->stream));
   }
   LBM_HIP(h, hipStreamSynchronize(h->stream));
   return LBM_OK;
@@ -376,24 +390,55 @@ int lbm_get_populations(lbm_handle* h, double* host) {
 int lbm_set_populations(lbm_handle* h, const double* host) {
   if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
   if (!host) return fail(h, LBM_EINVAL, "host is NULL");
+  if (h->geo.storage == STORAGE_F16DEV && !h->has_ref)
+    return fail(h, LBM_ESTATE, "deviation storage: set the reference density first");
   DeviceGuard dg(h->device);
   const Geometry& g = h->geo;
-  const size_t eb = elem_bytes(g);
   const size_t n = static_cast<size_t>(g.lx) * g.ly;
-  std::vector<float> tmp(g.storage == STORAGE_F32 ? n : 0);
+  double* stage = scratch(h);
   for (int l = 0; l < NPOP; ++l) {
-    const double* src = host + static_cast<size_t>(l) * n;
-    const void* stage = src;
-    if (g.storage == STORAGE_F32) {
-      for (size_t i = 0; i < n; ++i) tmp[i] = static_cast<float>(src[i]);  // round to nearest even
-      stage = tmp.data();
-    }
-    LBM_HIP(h, hipMemcpy2DAsync(current(h) + plane_col0(g, l), g.ny * eb, stage, g.ly * eb, g.ly * eb,
-                                g.lx, hipMemcpyHostToDevice, h->stream));
-    if (g.storage == STORAGE_F32) LBM_HIP(h, hipStreamSynchronize(h->stream));
+    LBM_HIP(h, hipMemcpyAsync(stage, host + static_cast<size_t>(l) * n, n * sizeof(double),
+                              hipMemcpyHostToDevice, h->stream));
+    LBM_HIP(h, launch_encode_plane(g, stage, current(h), l, h->stream));
   }
   LBM_HIP(h, hipStreamSynchronize(h->stream));
   h->ready = true;
+  return LBM_OK;
+}
+
+int lbm_set_reference(lbm_handle* h, const double* rho_ref) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
+  if (!rho_ref) return fail(h, LBM_EINVAL, "rho_ref is NULL");
+  if (h->geo.storage != STORAGE_F16DEV)
+    return fail(h, LBM_EINVAL, "a reference density exists only for LBM_FP16DEV storage");
+  const int ly = h->geo.ly;
+  std::vector<double> both(2 * static_cast<size_t>(ly));
+  for (int y = 0; y < ly; ++y) {
+    if (!std::isfinite(rho_ref[y]) || !(rho_ref[y] > 0.0))
+      return fail(h, LBM_EINVAL, "rho_ref must be finite and > 0");
+    both[y] = rho_ref[y];
+    both[ly + y] = 1.0 / rho_ref[y];
+  }
+  DeviceGuard dg(h->device);
+  LBM_HIP(h, hipMemcpyAsync(const_cast<double*>(h->geo.ref), both.data(), ly * sizeof(double),
+                            hipMemcpyHostToDevice, h->stream));
+  LBM_HIP(h, hipMemcpyAsync(const_cast<double*>(h->geo.inv_ref), both.data() + ly, ly * sizeof(double),
+                            hipMemcpyHostToDevice, h->stream));
+  LBM_HIP(h, hipStreamSynchronize(h->stream));
+  h->has_ref = true;
+  h->ready = false;  // stored deviations refer to the old reference
+  return LBM_OK;
+}
+
+int lbm_get_reference(lbm_handle* h, double* rho_ref) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
+  if (!rho_ref) return fail(h, LBM_EINVAL, "rho_ref is NULL");
+  if (h->geo.storage != STORAGE_F16DEV || !h->has_ref)
+    return fail(h, LBM_ESTATE, "no reference density (LBM_FP16DEV only, after init or set)");
+  DeviceGuard dg(h->device);
+  LBM_HIP(h, hipMemcpyAsync(rho_ref, h->geo.ref, h->geo.ly * sizeof(double), hipMemcpyDeviceToHost,
+                            h->stream));
+  LBM_HIP(h, hipStreamSynchronize(h->stream));
   return LBM_OK;
 }
 

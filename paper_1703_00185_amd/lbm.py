@@ -22,7 +22,7 @@ LIB_PATH = os.environ.get("PAPER_1703_00185_AMD_LIB") or os.path.join(
 NPOP = 37
 MAX_MODES = 32
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ESTATE = 0, -1, -2, -3, -4
-LBM_FP64, LBM_FP32 = 0, 1
+LBM_FP64, LBM_FP32, LBM_FP16DEV = 0, 1, 2
 LBM_PATH_SEPARATE, LBM_PATH_FUSED = 0, 1
 (LBM_PHASE_PBC, LBM_PHASE_PROPAGATE, LBM_PHASE_BC, LBM_PHASE_COLLIDE,
  LBM_PHASE_FUSED) = range(5)
@@ -75,6 +75,8 @@ def load():
         "lbm_get_populations": (c_int, [H, c_void_p]),
         "lbm_set_populations": (c_int, [H, c_void_p]),
         "lbm_get_sites": (c_int, [H, c_int32, c_void_p, c_void_p, c_void_p]),
+        "lbm_set_reference": (c_int, [H, c_void_p]),
+        "lbm_get_reference": (c_int, [H, c_void_p]),
         "lbm_set_timing": (c_int, [H, c_int32]),
         "lbm_read_timing": (c_int, [H, c_void_p, c_void_p]),
         "lbm_layout": (c_int, [H, c_void_p]),
@@ -183,6 +185,17 @@ def lbm_get_sites(h, xs, ys) -> np.ndarray:
         raise ValueError("xs and ys must be 1-D arrays of equal length")
     out = np.empty((NPOP, xs.size), dtype=np.float64)
     _check(load().lbm_get_sites(h, xs.size, _ptr(xs), _ptr(ys), _ptr(out)), h)
+    return out
+
+
+def lbm_set_reference(h, rho_ref) -> None:
+    rho_ref = np.ascontiguousarray(rho_ref, dtype=np.float64)
+    _check(load().lbm_set_reference(h, _ptr(rho_ref)), h)
+
+
+def lbm_get_reference(h, ly: int) -> np.ndarray:
+    out = np.empty(ly, dtype=np.float64)
+    _check(load().lbm_get_reference(h, _ptr(out)), h)
     return out
 
 

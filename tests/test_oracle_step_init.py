@@ -121,3 +121,25 @@ def test_fp32_storage_rounds_every_value_once():
     # interior rows equal for both sequences; wall rows see one extra rounding
     sep = oracle.step_stored(f, cfg, "fp32", False)
     assert np.array_equal(sep[:, :, 3:17], got[:, :, 3:17])
+
+
+def test_fp16dev_encoding_properties():
+    """Deviation storage: the reference state itself encodes to d = 0 and
+    decodes exactly; a value c (1 + d) with d a binary16 number round-trips
+    bit for bit; and the decoded value is within half a binary16 ulp of d
+    (relative to c) of the original."""
+    k = oracle.constants()
+    ly = 16
+    ref = np.linspace(0.7, 1.4, ly)
+    c = k.w[:, None, None] * ref[None, None, :]
+    c3 = np.broadcast_to(c, (37, 2, ly)).copy()
+    assert np.all(oracle.encode_fp16dev(c3, ref) == 0)
+    assert np.array_equal(oracle.decode_fp16dev(oracle.encode_fp16dev(c3, ref), ref), c3)
+    d = inputs.noise(3, (37, 2, ly), 0.2).astype(np.float16)
+    f = oracle.decode_fp16dev(d, ref)
+    assert np.array_equal(oracle.encode_fp16dev(f, ref), d)
+    g = c3 * (1 + inputs.noise(4, (37, 2, ly), 0.2))
+    back = oracle.stored(g, "fp16dev", ref)
+    dev = (g - c3) / c3
+    tol = np.spacing(np.abs(dev).astype(np.float16)).astype(np.float64) * 0.5 * (1 + 2.0 ** -12) + 1e-12
+    assert np.all(np.abs((back - g) / c3) <= tol)
