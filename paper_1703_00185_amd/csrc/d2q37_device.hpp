@@ -1,0 +1,207 @@
+// Site-local device code of the D2Q37 step, shared by the single-lattice
+// kernels and the ensemble engine: storage codecs, moment sums, the BGK
+// collision and the thermal-wall reset.  Included by .hip files only; the
+// including file must compile without floating-point contraction (every
+// fused multiply-add below is an explicit fma()).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#pragma clang fp contract(off)
+
+#include "kernels.hpp"
+
+namespace d2q37 {
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int NXCD = 8;  // accelerator complex dies of an MI355X
+
+// Work-group ids are dealt round-robin over the 8 XCDs, each with its own
+// L2.  Renumber them so that each XCD runs one contiguous range of logical
+// tiles: neighbouring y-tiles of a column then share the 512-byte segments
+// that straddle their boundary (the +-3-row misalignment of the pull) in
+// the same L2.  Bijective for any number of groups.
+__device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
+  const int xcd = bid % NXCD;
+  const int idx = bid / NXCD;
+  const int q = nblocks / NXCD;
+  const int r = nblocks % NXCD;
+  return xcd * q + (xcd < r ? xcd : r) + idx;
+}
+
+// Raw element access at a byte offset from a wavefront-uniform base.
+template <class S>
+__device__ __forceinline__ S ld(const S* base, unsigned byte_off) {
+  return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <class S>
+__device__ __forceinline__ void st(S* base, unsigned byte_off, S v) {
+  *reinterpret_cast<S*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
+// Population storage codecs.  Arithmetic is binary64 for every storage;
+// a codec turns the stored element of population l at row y into the
+// binary64 population and back.
+//  * binary64: identity.
+//  * binary32: exact widening; rounding to nearest on store.
+//  * binary16 deviation: the element is d = (f - c) / c with the reference
+//    c = w_l rho_ref(y) (a per-row reference density); stored as
+//    d = f16(f32((f - c) * (w_l^-1 * rho_ref(y)^-1))) and read back as
+//    c (1 + d).  1 + d is exact in binary64, so decoding rounds once.
+struct CodecF64 {
+  using S = double;
+  const double* ref;
+  const double* inv_ref;
+  __device__ double dec(S v, int, int) const { return v; }
+  __device__ S enc(double f, int, int) const { return f; }
+};
+struct CodecF32 {
+  using S = float;
+  const double* ref;
+  const double* inv_ref;
+  __device__ double dec(S v, int, int) const { return static_cast<double>(v); }
+  __device__ S enc(double f, int, int) const { return static_cast<float>(f); }
+};
+struct CodecF16Dev {
+  using S = _Float16;
+  const double* ref;
+  const double* inv_ref;
+  __device__ double dec(S v, int l, int y) const {
+    const double c = weight_of(l) * ref[y];
+    return c * (1.0 + static_cast<double>(static_cast<float>(v)));
+  }
+  __device__ S enc(double f, int l, int y) const {
+    const double c = weight_of(l) * ref[y];
+    const double q = (f - c) * (inv_weight_of(l) * inv_ref[y]);
+    return static_cast<_Float16>(static_cast<float>(q));
+  }
+};
+
+// acc + k * v for a small integer k known after unrolling.
+__device__ __forceinline__ double add_scaled(double acc, int k, double v) {
+  if (k == 0) return acc;
+  if (k == 1) return acc + v;
+  if (k == -1) return acc - v;
+  return fma(static_cast<double>(k), v, acc);
+}
+// k * v for a small integer k known after unrolling.
+__device__ __forceinline__ double scaled(int k, double v) {
+  if (k == 1) return v;
+  if (k == -1) return -v;
+  return static_cast<double>(k) * v;
+}
+
+// ---------------------------------------------------------------------------
+// Site-local arithmetic
+// ---------------------------------------------------------------------------
+
+// Moment sums of one site: rho = sum f, jx = sum e_x f, jy = sum e_y f,
+// eps = sum |e|^2 f (integer hops; velocities are r e).  Populations are
+// summed pairwise (l, opp(l)) and shell by shell.
+struct MomentSums {
+  double rho, jx, jy, eps;
+};
+
+__device__ __forceinline__ MomentSums moment_sums(const double (&f)[NPOP]) {
+  double shell[NSHELL];
+  double jx = 0.0, jy = 0.0;
+  shell[0] = f[0];
+#pragma unroll
+  for (int s = 1; s < NSHELL; ++s) {
+    const int lo = SHELL_START[s], hi = SHELL_START[s + 1], mid = (lo + hi) / 2;
+    double acc = 0.0;
+#pragma unroll
+    for (int l = lo; l < mid; ++l) {
+      const int m = lo + hi - 1 - l;  // opposite population: e_m = -e_l
+      const double sum = f[m] + f[l];
+      const double dif = f[m] - f[l];
+      acc = (l == lo) ? sum : acc + sum;
+      jx = add_scaled(jx, EX[m], dif);
+      jy = add_scaled(jy, EY[m], dif);
+    }
+    shell[s] = acc;
+  }
+  double rho = shell[0];
+  double eps = shell[1];
+#pragma unroll
+  for (int s = 1; s < NSHELL; ++s) rho = rho + shell[s];
+#pragma unroll
+  for (int s = 2; s < NSHELL; ++s) eps = fma(static_cast<double>(SHELL_N2[s]), shell[s], eps);
+  return {rho, jx, jy, eps};
+}
+
+// BGK collision of one site (Eqs. 4-6): moments, shifted fields
+// u + tau g and T - tau^2 |g|^2 / 2, the 4th-order Hermite equilibrium, and
+// f <- (1 - omega) f + omega f^eq.  The equilibrium of population l is
+// rho w_l P(s), s = u_shift . c_l, with per-shell coefficients
+//   P(s) = p0 + p1 s + p2 s^2 + s^3/6 + s^4/24,
+//   p0 = 1 - U/2 + U^2/8 + th (C-2)/2 + th U (4-C)/4 + th^2 (C^2-8C+8)/8,
+//   p1 = 1 - U/2 + th (C-4)/2,   p2 = 1/2 - U/4 + th (C-6)/4,
+// U = |u_shift|^2, th = T_shift - 1, C = |c_l|^2.  The even and odd parts
+// of P serve both populations of a pair (s changes sign).
+__device__ __forceinline__ void collide_site(double (&f)[NPOP], const CollideParams& p) {
+  const MomentSums m = moment_sums(f);
+  const double inv_rho = 1.0 / m.rho;
+  const double ux = R * m.jx * inv_rho;
+  const double uy = R * m.jy * inv_rho;
+  const double temp = 0.5 * (R2 * m.eps * inv_rho - (ux * ux + uy * uy));
+  const double ubx = ux + p.tgx;
+  const double uby = uy + p.tgy;
+  const double th = (temp - p.dtemp) - 1.0;
+  const double U = ubx * ubx + uby * uby;
+  const double vx = R * ubx;
+  const double vy = R * uby;
+  const double th2 = th * th;
+  // p0 = a0 + C (b0 + C d0), p1 = a1 + C b1, p2 = a2 + C b2
+  const double a0 = (((1.0 - 0.5 * U) + 0.125 * U * U) - th) + (th * U + th2);
+  const double b0 = (0.5 * th - 0.25 * th * U) - th2;
+  const double d0 = 0.125 * th2;
+  const double a1 = (1.0 - 0.5 * U) - 2.0 * th;
+  const double b1 = 0.5 * th;
+  const double a2 = (0.5 - 0.25 * U) - 1.5 * th;
+  const double b2 = 0.25 * th;
+  const double rw = m.rho * p.omega;
+  const double om1 = p.one_minus_omega;
+
+  f[0] = fma(om1, f[0], (rw * W_SHELL[0]) * a0);
+#pragma unroll
+  for (int s = 1; s < NSHELL; ++s) {
+    const double C = R2 * static_cast<double>(SHELL_N2[s]);
+    const double cs = rw * W_SHELL[s];
+    const double e0 = cs * fma(C, fma(C, d0, b0), a0);
+    const double e2 = cs * fma(C, b2, a2);
+    const double e4 = cs * (1.0 / 24.0);
+    const double o1 = cs * fma(C, b1, a1);
+    const double o3 = cs * (1.0 / 6.0);
+    const int lo = SHELL_START[s], hi = SHELL_START[s + 1], mid = (lo + hi) / 2;
+#pragma unroll
+    for (int l = lo; l < mid; ++l) {
+      const int mm = lo + hi - 1 - l;
+      double sv;
+      if (EX[mm] == 0)
+        sv = scaled(EY[mm], vy);
+      else if (EY[mm] == 0)
+        sv = scaled(EX[mm], vx);
+      else
+        sv = add_scaled(scaled(EX[mm], vx), EY[mm], vy);
+      const double ss = sv * sv;
+      const double even = fma(ss, fma(ss, e4, e2), e0);
+      const double odd = sv * fma(ss, o3, o1);
+      f[mm] = fma(om1, f[mm], even + odd);
+      f[l] = fma(om1, f[l], even - odd);
+    }
+  }
+}
+
+// bc of one wall-row site: rho = f_0 + ... + f_36 (left fold), f_l = rho K_l.
+__device__ __forceinline__ void thermalise(double (&f)[NPOP], bool bottom, const WallParams& w) {
+  double rho = f[0];
+#pragma unroll
+  for (int l = 1; l < NPOP; ++l) rho = rho + f[l];
+#pragma unroll
+  for (int l = 0; l < NPOP; ++l) f[l] = rho * (bottom ? w.kb[l] : w.kt[l]);
+}
+
+}  // namespace
+}  // namespace d2q37
