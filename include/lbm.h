@@ -211,6 +211,77 @@ typedef enum { LBM_PROBE_COPY = 0, LBM_PROBE_MRAW = 1, LBM_PROBE_ARMW = 2 } lbm_
 int lbm_probe_bandwidth(int32_t mode, const void *src, void *dst, size_t bytes, int32_t shift,
                         void *stream);
 
+/* ------------------------------------------------------------------------
+ * Ensemble engine: many independent lattices stepped together, one
+ * persistent launch per time step (the step of Eq. 6 for every lattice,
+ * fused as above, periodic x by wrapping the source column instead of pbc),
+ * replayed from a HIP graph built once.  Lattices are existing handles
+ * (LBM_FP64 or LBM_FP32 storage, any sizes, each with its own tau, g and
+ * walls); each keeps its own step count and stops when it reaches zero.
+ * The engine owns no lattice memory: its own device block (caller-owned,
+ * lbm_engine_required_bytes) holds the slot table only.
+ *
+ * While a lattice is in an engine, the engine steps it on the engine's
+ * stream (the handle is rebound to that stream); lbm_step, lbm_run_phase,
+ * lbm_init_rt, lbm_set_populations and lbm_set_reference on it fail with
+ * ESTATE; reads (moments, conservation, populations, sites) first
+ * synchronise with the engine.  lbm_destroy of such a handle removes it
+ * from its engine first.
+ * ---------------------------------------------------------------------- */
+typedef struct lbm_engine lbm_engine;
+
+/* Engine schedules (how work-groups of the persistent grid take tiles):
+ * CHUNKED = one contiguous run of tiles per work-group; STRIDED = tiles
+ * dealt round-robin.  A tile is `block` rows of one column of one lattice. */
+typedef enum { LBM_SCHED_CHUNKED = 0, LBM_SCHED_STRIDED = 1 } lbm_schedule;
+
+/* Bytes of device memory for an engine with max_slots lattices; 0 if
+ * max_slots is outside [1, 2^20]. */
+size_t lbm_engine_required_bytes(int32_t max_slots);
+
+/* Create an engine on caller memory (256-byte aligned) and stream.
+ * Default tiling: block 256, 4 work-groups per compute unit, CHUNKED.
+ * Errors: EINVAL, ENOMEM (block too small / misaligned), EDEVICE. */
+int lbm_engine_create(int32_t max_slots, void *dev_mem, size_t dev_bytes, void *stream,
+                      lbm_engine **out);
+
+/* Add lattice h with `steps` steps to run; *slot receives its slot index.
+ * Synchronises h's stream first.  Errors: EINVAL (NULL, other storage,
+ * other device, steps < 0), ESTATE (h not initialised or already in an
+ * engine), ENOMEM (no free slot), EDEVICE. */
+int lbm_engine_add(lbm_engine *e, lbm_handle *h, int32_t steps, int32_t *slot);
+
+/* Take the lattice of `slot` out of the engine (its state stays in its
+ * handle, at the step it reached).  Synchronises the engine stream. */
+int lbm_engine_remove(lbm_engine *e, int32_t slot);
+
+/* Enqueue n engine steps (asynchronous): each lattice with steps left
+ * advances one step per engine step. */
+int lbm_engine_step(lbm_engine *e, int32_t n);
+
+/* Synchronise and report steps left per slot (steps_left[max_slots];
+ * -1 for a free slot; may be NULL).  Finished lattices leave the tile table. */
+int lbm_engine_status(lbm_engine *e, int32_t *steps_left);
+
+/* Tiling: block (64, 128, 256, 512 rows per tile), persistent groups, and
+ * lbm_schedule.  set_tiling rebuilds the step graph. */
+int lbm_engine_set_tiling(lbm_engine *e, int32_t block, int32_t groups, int32_t schedule);
+int lbm_engine_get_tiling(const lbm_engine *e, int32_t out[3]);
+
+/* Autotune the tiling on the current lattices: times `reps` step launches
+ * (without advancing any lattice: each launch rewrites the idle buffer from
+ * the current one) for every block in {64,128,256,512}, groups in
+ * {1,2,4,8,16} x compute units and both schedules; keeps the fastest.
+ * out[3] = chosen (block, groups, schedule), *best_ms = its time per step
+ * (either may be NULL).  Errors: ESTATE (no active lattice), EDEVICE. */
+int lbm_engine_tune(lbm_engine *e, int32_t reps, int32_t out[3], double *best_ms);
+
+/* Reason of the last engine failure (per engine, or per thread for NULL). */
+const char *lbm_engine_last_error(const lbm_engine *e);
+
+/* Release the engine; its lattices keep their state (cur written back). */
+void lbm_engine_destroy(lbm_engine *e);
+
 /* Reason of the last failure on h, or of the last failed lbm_create /
  * lbm_required_bytes on this thread when h is NULL.  Never NULL. */
 const char *lbm_last_error(const lbm_handle *h);

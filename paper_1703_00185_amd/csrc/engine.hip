@@ -1,0 +1,212 @@
+// Ensemble engine kernels: one persistent launch steps every active lattice
+// (propagate + bc + collide, as the fused kernel, with periodic x done by
+// wrapping the source column), and a small kernel advances each lattice's
+// double buffer and step count.
+//
+// Work decomposition: a tile is BLOCK consecutive rows of one column of one
+// lattice; the tiles of all active lattices form one index space, in the
+// order of the active-slot table.  The grid is persistent (a fixed number
+// of work-groups).  CHUNKED gives each work-group one contiguous run of
+// tiles, so neighbouring tiles of a column run on the same CU and share the
+// cache lines the +-3-row pull straddles, and the lattice of the next tile
+// is found by stepping through the prefix table.  STRIDED deals tiles
+// round-robin and finds each tile's lattice by binary search.
+#pragma clang fp contract(off)
+
+#include "d2q37_device.hpp"
+#include "engine.hpp"
+
+namespace d2q37 {
+namespace {
+
+// Lattice buffers are read from the slot table, so the compiler cannot
+// know they are global memory; these pointers say so, which keeps loads
+// and stores in the global (not flat) address mode.
+#define GLOBAL_AS __attribute__((address_space(1)))
+
+// Source column of population l for a tile at column x: periodic wrap.
+// x is uniform over the work-group, so this is scalar arithmetic.
+__device__ __forceinline__ int wrap_col(int x, int ex, int lx) {
+  int xs = x - ex;
+  if (xs < 0) xs += lx;
+  if (xs >= lx) xs -= lx;
+  return xs;
+}
+
+template <class C>
+__device__ __forceinline__ void gather_wrap_interior(const SlotDesc& d, const C& cd,
+                                                     const GLOBAL_AS typename C::S* src, int x, int y,
+                                                     double (&f)[NPOP]) {
+  using S = typename C::S;
+  const unsigned uy = static_cast<unsigned>(y);
+#pragma unroll
+  for (int l = 0; l < NPOP; ++l) {
+    const int col = wrap_col(x, EX[l], d.lx) + HALO;
+    const GLOBAL_AS S* base =
+        src + (static_cast<long long>(l) * d.plane + static_cast<long long>(col) * d.ny - EY[l]);
+    f[l] = cd.dec(base[uy], l, y - EY[l]);
+  }
+}
+
+template <class C>
+__device__ __forceinline__ void gather_wrap_wall(const SlotDesc& d, const C& cd,
+                                                 const GLOBAL_AS typename C::S* src, int x, int y,
+                                                 double (&f)[NPOP]) {
+#pragma unroll
+  for (int l = 0; l < NPOP; ++l) {
+    const int ys = y - EY[l];
+    const bool inside = (ys >= 0) && (ys < d.ly);
+    const long long col = wrap_col(x, EX[l], d.lx) + HALO;
+    const long long idx = inside
+        ? static_cast<long long>(l) * d.plane + col * d.ny + ys
+        : static_cast<long long>(opp_of(l)) * d.plane + static_cast<long long>(x + HALO) * d.ny + y;
+    f[l] = cd.dec(src[idx], l, inside ? ys : y);
+  }
+}
+
+// One tile: rows yb*BLOCK .. of column x of lattice d, from buffer cur to
+// the other buffer.  Same arithmetic as the single-lattice fused kernel.
+template <class C, int BLOCK>
+__device__ __forceinline__ void step_tile(const SlotDesc& d, int x, int yb) {
+  using S = typename C::S;
+  const C cd{nullptr, nullptr};
+  const GLOBAL_AS S* src = (const GLOBAL_AS S*)(d.buf[d.cur]);
+  GLOBAL_AS S* dst = (GLOBAL_AS S*)(d.buf[d.cur ^ 1]);
+  const int y = yb * BLOCK + static_cast<int>(threadIdx.x);
+  const int ywave = yb * BLOCK + static_cast<int>(threadIdx.x & ~(WAVE - 1));
+  double f[NPOP];
+  const int interior = (ywave >= WALL_ROWS) && (ywave + WAVE <= d.ly - WALL_ROWS);
+  if (__builtin_amdgcn_readfirstlane(interior)) {
+    gather_wrap_interior(d, cd, src, x, y, f);
+  } else {
+    const int yc = y < d.ly ? y : d.ly - 1;
+    gather_wrap_wall(d, cd, src, x, yc, f);
+    if (yc < WALL_ROWS || yc >= d.ly - WALL_ROWS) thermalise(f, yc < WALL_ROWS, d.wp);
+  }
+  collide_site(f, d.cp);
+  if (y < d.ly) {
+    const unsigned site = static_cast<unsigned>(y);
+    GLOBAL_AS S* col = dst + static_cast<long long>(x + HALO) * d.ny;
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) (col + static_cast<long long>(l) * d.plane)[site] = cd.enc(f[l], l, y);
+  }
+}
+
+template <class C, int BLOCK>
+__device__ __forceinline__ void run_tile(const SlotDesc& d, int local) {
+  if (d.steps_left <= 0) return;
+  // the tile coordinates are uniform over the work-group: keep them (and
+  // every address derived from them) in scalar registers
+  const int x = __builtin_amdgcn_readfirstlane(local / d.ny_blocks);
+  const int yb = __builtin_amdgcn_readfirstlane(local - x * d.ny_blocks);
+  step_tile<C, BLOCK>(d, x, yb);
+}
+
+// One kernel per storage type (C): each walks the tile table of the
+// lattices of its type.
+template <class C, int BLOCK, int SCHED>
+__global__ void __launch_bounds__(BLOCK) engine_step_kernel(const SlotDesc* __restrict__ slots,
+                                                            const int* __restrict__ table,
+                                                            int max_slots) {
+  const int n = table[0];
+  const int total = table[1];
+  const int* order = table + 2;
+  const int* start = table + 2 + max_slots;
+  if (n <= 0 || total <= 0) return;
+  if (SCHED == SCHED_CHUNKED) {
+    const long long g = gridDim.x, b = blockIdx.x;
+    const int t0 = static_cast<int>(total * b / g);
+    const int t1 = static_cast<int>(total * (b + 1) / g);
+    if (t0 >= t1) return;
+    int lo = 0, hi = n - 1;  // last k with start[k] <= t0
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (start[mid] <= t0) lo = mid; else hi = mid - 1;
+    }
+    int k = lo;
+    for (int t = t0; t < t1; ++t) {
+      while (t >= start[k + 1]) ++k;
+      run_tile<C, BLOCK>(slots[order[k]], t - start[k]);
+    }
+  } else {
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+      int lo = 0, hi = n - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= t) lo = mid; else hi = mid - 1;
+      }
+      run_tile<C, BLOCK>(slots[order[lo]], t - start[lo]);
+    }
+  }
+}
+
+// After a step: flip the buffer and count the step for every slot that
+// still had steps to run (free slots hold steps_left = 0); publish
+// (steps_left, cur) per slot.
+__global__ void __launch_bounds__(256) engine_advance_kernel(SlotDesc* __restrict__ slots,
+                                                             int max_slots, int* __restrict__ status) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= max_slots) return;
+  SlotDesc& d = slots[s];
+  if (d.steps_left > 0) {
+    d.cur ^= 1;
+    d.steps_left -= 1;
+  }
+  status[2 * s] = d.steps_left;
+  status[2 * s + 1] = d.cur;
+}
+
+template <class C, int SCHED>
+void* step_func(int block) {
+  switch (block) {
+    case 64: return reinterpret_cast<void*>(&engine_step_kernel<C, 64, SCHED>);
+    case 128: return reinterpret_cast<void*>(&engine_step_kernel<C, 128, SCHED>);
+    case 256: return reinterpret_cast<void*>(&engine_step_kernel<C, 256, SCHED>);
+    case 512: return reinterpret_cast<void*>(&engine_step_kernel<C, 512, SCHED>);
+    default: return nullptr;
+  }
+}
+
+template <class C>
+void* step_func(int block, int schedule) {
+  return schedule == SCHED_STRIDED ? step_func<C, SCHED_STRIDED>(block) : step_func<C, SCHED_CHUNKED>(block);
+}
+
+}  // namespace
+
+hipError_t engine_step_node(int storage, int block, int groups, int schedule, void** func, dim3* grid,
+                            dim3* threads) {
+  void* f = storage == STORAGE_F32 ? step_func<CodecF32>(block, schedule) : step_func<CodecF64>(block, schedule);
+  if (!f || groups <= 0) return hipErrorInvalidValue;
+  *func = f;
+  *grid = dim3(groups);
+  *threads = dim3(block);
+  return hipSuccess;
+}
+
+hipError_t engine_advance_node(int max_slots, void** func, dim3* grid, dim3* threads) {
+  *func = reinterpret_cast<void*>(&engine_advance_kernel);
+  *grid = dim3((max_slots + 255) / 256);
+  *threads = dim3(256);
+  return hipSuccess;
+}
+
+hipError_t launch_engine_step(int storage, const SlotDesc* slots, const int* table, int max_slots,
+                              int block, int groups, int schedule, hipStream_t s) {
+  void* f;
+  dim3 grid, threads;
+  hipError_t e = engine_step_node(storage, block, groups, schedule, &f, &grid, &threads);
+  if (e != hipSuccess) return e;
+  void* args[] = {&slots, &table, &max_slots};
+  (void)hipGetLastError();
+  return hipLaunchKernel(f, grid, threads, args, 0, s);
+}
+
+hipError_t launch_engine_advance(SlotDesc* slots, int max_slots, int* status, hipStream_t s) {
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(engine_advance_kernel, dim3((max_slots + 255) / 256), dim3(256), 0, s, slots,
+                     max_slots, status);
+  return hipGetLastError();
+}
+
+}  // namespace d2q37

@@ -10,61 +10,18 @@
 #include <string>
 #include <vector>
 
+#include "internal.hpp"
 #include "kernels.hpp"
 #include "lbm.h"
 
 using namespace d2q37;
-
-struct lbm_handle {
-  lbm_config cfg{};
-  Geometry geo{};
-  size_t buf_bytes = 0;
-  char* buf[2] = {nullptr, nullptr};
-  int cur = 0;  // buffer holding the current populations
-  hipStream_t stream = nullptr;
-  int device = 0;
-  bool ready = false;
-  bool has_ref = false;  // deviation storage: reference density set
-  CollideParams cp{};
-  WallParams wp{};
-  std::string err;
-  // per-launch timing
-  bool timing = false;
-  std::vector<hipEvent_t> events;
-  size_t ev_used = 0;
-  struct Rec {
-    int phase;
-    size_t ev;
-  };
-  std::vector<Rec> recs;
-};
+using namespace d2q37::host;
 
 namespace {
-
-thread_local std::string g_err;
-
-int fail(lbm_handle* h, int code, const std::string& msg) {
-  if (h)
-    h->err = msg;
-  else
-    g_err = msg;
-  return code;
-}
-
-#define LBM_HIP(h, expr)                                                              \
-  do {                                                                                \
-    hipError_t e_ = (expr);                                                           \
-    if (e_ != hipSuccess)                                                             \
-      return fail((h), LBM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-  } while (0)
 
 constexpr long long kMaxPlaneElems = (1LL << 29);  // byte offsets inside a plane fit 32 bits
 
 long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
-
-int elem_bytes(const Geometry& g) {
-  return g.storage == STORAGE_F32 ? 4 : g.storage == STORAGE_F16DEV ? 2 : 8;
-}
 
 struct Layout {
   Geometry geo;
@@ -117,21 +74,6 @@ int make_layout(const lbm_config* c, Layout* out, std::string* why) {
     return *why = "internal: staging does not fit", LBM_EINVAL;
   return LBM_OK;
 }
-
-// Make the handle's device current for the duration of a call.
-struct DeviceGuard {
-  int prev = -1, want;
-  explicit DeviceGuard(int d) : want(d) {
-    if (hipGetDevice(&prev) == hipSuccess && prev != want) (void)hipSetDevice(want);
-  }
-  ~DeviceGuard() {
-    if (prev >= 0 && prev != want) (void)hipSetDevice(prev);
-  }
-};
-
-char* other(lbm_handle* h) { return h->buf[h->cur ^ 1]; }
-char* current(lbm_handle* h) { return h->buf[h->cur]; }
-double* scratch(lbm_handle* h) { return reinterpret_cast<double*>(other(h)); }
 
 // Byte offset of physical column 0 of population l.
 size_t plane_col0(const Geometry& g, int l) {
@@ -287,6 +229,7 @@ int lbm_init_rt(lbm_handle* h, const lbm_rt_params* rt) {
   if (rt->n_modes < 0 || rt->n_modes > LBM_MAX_MODES)
     return fail(h, LBM_EINVAL, "n_modes must be in [0, 32]");
   if (rt->n_modes > 0 && (!rt->amp || !rt->phase)) return fail(h, LBM_EINVAL, "amp/phase are NULL");
+  if (h->engine) return fail(h, LBM_ESTATE, "lattice is stepped by an engine (remove it first)");
   RtParams p{};
   p.tm = 0.5 * (h->cfg.t_bottom + h->cfg.t_top);
   p.a = 0.5 * (h->cfg.t_bottom - h->cfg.t_top);
@@ -315,6 +258,7 @@ int lbm_step(lbm_handle* h, int32_t n) {
   if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
   if (n < 0) return fail(h, LBM_EINVAL, "n must be >= 0");
   if (!h->ready) return fail(h, LBM_ESTATE, "lattice not initialised");
+  if (h->engine) return fail(h, LBM_ESTATE, "lattice is stepped by an engine (remove it first)");
   DeviceGuard dg(h->device);
   for (int32_t i = 0; i < n; ++i) {
     int rc = run_phase(h, LBM_PHASE_PBC);
@@ -336,6 +280,7 @@ int lbm_run_phase(lbm_handle* h, int32_t phase) {
   if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
   if (phase < 0 || phase >= LBM_NPHASES) return fail(h, LBM_EINVAL, "unknown phase");
   if (!h->ready) return fail(h, LBM_ESTATE, "lattice not initialised");
+  if (h->engine) return fail(h, LBM_ESTATE, "lattice is stepped by an engine (remove it first)");
   DeviceGuard dg(h->device);
   return run_phase(h, phase);
 }
@@ -343,6 +288,8 @@ int lbm_run_phase(lbm_handle* h, int32_t phase) {
 int lbm_moments(lbm_handle* h, double* rho, double* ux, double* uy, double* T) {
   if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
   if (!h->ready) return fail(h, LBM_ESTATE, "lattice not initialised");
+  if (h->engine && engine_refresh(h->engine) != LBM_OK)
+    return fail(h, LBM_EDEVICE, "engine status refresh failed");
   DeviceGuard dg(h->device);
   double* tmp = scratch(h);
   LBM_HIP(h, launch_moments(h->geo, current(h), tmp, h->stream));
@@ -360,6 +307,8 @@ int lbm_conservation(lbm_handle* h, double out[5]) {
   if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
   if (!out) return fail(h, LBM_EINVAL, "out is NULL");
   if (!h->ready) return fail(h, LBM_ESTATE, "lattice not initialised");
+  if (h->engine && engine_refresh(h->engine) != LBM_OK)
+    return fail(h, LBM_EDEVICE, "engine status refresh failed");
   DeviceGuard dg(h->device);
   double* partials = scratch(h);
   double* result = partials + CONS_BLOCKS * CONS_FIELDS;
@@ -374,6 +323,8 @@ int lbm_get_populations(lbm_handle* h, double* host) {
   if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
   if (!host) return fail(h, LBM_EINVAL, "host is NULL");
   if (!h->ready) return fail(h, LBM_ESTATE, "lattice not initialised");
+  if (h->engine && engine_refresh(h->engine) != LBM_OK)
+    return fail(h, LBM_EDEVICE, "engine status refresh failed");
   DeviceGuard dg(h->device);
   const Geometry& g = h->geo;
   const size_t n = static_cast<size_t>(g.lx) * g.ly;
@@ -392,6 +343,7 @@ int lbm_set_populations(lbm_handle* h, const double* host) {
   if (!host) return fail(h, LBM_EINVAL, "host is NULL");
   if (h->geo.storage == STORAGE_F16DEV && !h->has_ref)
     return fail(h, LBM_ESTATE, "deviation storage: set the reference density first");
+  if (h->engine) return fail(h, LBM_ESTATE, "lattice is stepped by an engine (remove it first)");
   DeviceGuard dg(h->device);
   const Geometry& g = h->geo;
   const size_t n = static_cast<size_t>(g.lx) * g.ly;
@@ -408,6 +360,7 @@ int lbm_set_populations(lbm_handle* h, const double* host) {
 
 int lbm_set_reference(lbm_handle* h, const double* rho_ref) {
   if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
+  if (h->engine) return fail(h, LBM_ESTATE, "lattice is stepped by an engine (remove it first)");
   if (!rho_ref) return fail(h, LBM_EINVAL, "rho_ref is NULL");
   if (h->geo.storage != STORAGE_F16DEV)
     return fail(h, LBM_EINVAL, "a reference density exists only for LBM_FP16DEV storage");
@@ -448,6 +401,8 @@ int lbm_get_sites(lbm_handle* h, int32_t n, const int32_t* xs, const int32_t* ys
   if (n == 0) return LBM_OK;
   if (!xs || !ys || !out) return fail(h, LBM_EINVAL, "xs/ys/out are NULL");
   if (!h->ready) return fail(h, LBM_ESTATE, "lattice not initialised");
+  if (h->engine && engine_refresh(h->engine) != LBM_OK)
+    return fail(h, LBM_EDEVICE, "engine status refresh failed");
   const size_t per_site = NPOP * sizeof(double) + 2 * sizeof(int);  // 304 bytes
   if (static_cast<size_t>(n) > h->buf_bytes / per_site)
     return fail(h, LBM_EINVAL, "too many sites for the scratch copy");
@@ -542,6 +497,7 @@ const char* lbm_last_error(const lbm_handle* h) { return h ? h->err.c_str() : g_
 
 void lbm_destroy(lbm_handle* h) {
   if (!h) return;
+  if (h->engine) engine_detach(h->engine, h->engine_slot);
   {
     DeviceGuard dg(h->device);
     (void)hipStreamSynchronize(h->stream);

@@ -83,6 +83,17 @@ def load():
         "lbm_tables": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
         "lbm_wall_factors": (c_int, [c_double, c_void_p]),
         "lbm_probe_bandwidth": (c_int, [c_int32, c_void_p, c_void_p, c_size_t, c_int32, c_void_p]),
+        "lbm_engine_required_bytes": (c_size_t, [c_int32]),
+        "lbm_engine_create": (c_int, [c_int32, c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]),
+        "lbm_engine_add": (c_int, [c_void_p, H, c_int32, c_void_p]),
+        "lbm_engine_remove": (c_int, [c_void_p, c_int32]),
+        "lbm_engine_step": (c_int, [c_void_p, c_int32]),
+        "lbm_engine_status": (c_int, [c_void_p, c_void_p]),
+        "lbm_engine_set_tiling": (c_int, [c_void_p, c_int32, c_int32, c_int32]),
+        "lbm_engine_get_tiling": (c_int, [c_void_p, c_void_p]),
+        "lbm_engine_tune": (c_int, [c_void_p, c_int32, c_void_p, c_void_p]),
+        "lbm_engine_last_error": (c_char_p, [c_void_p]),
+        "lbm_engine_destroy": (None, [c_void_p]),
         "lbm_last_error": (c_char_p, [H]),
         "lbm_destroy": (None, [H]),
     }
@@ -243,6 +254,69 @@ def lbm_destroy(h) -> None:
     load().lbm_destroy(h)
 
 
+LBM_SCHED_CHUNKED, LBM_SCHED_STRIDED = 0, 1
+
+
+def _echeck(status: int, e=None) -> None:
+    if status != LBM_OK:
+        msg = load().lbm_engine_last_error(e)
+        raise LbmError(status, msg.decode() if msg else "")
+
+
+def lbm_engine_required_bytes(max_slots: int) -> int:
+    n = load().lbm_engine_required_bytes(max_slots)
+    if n == 0:
+        _echeck(LBM_EINVAL)
+    return int(n)
+
+
+def lbm_engine_create(max_slots: int, dev_mem: int, dev_bytes: int, stream: int) -> c_void_p:
+    e = c_void_p()
+    _echeck(load().lbm_engine_create(max_slots, c_void_p(dev_mem), dev_bytes, c_void_p(stream), byref(e)))
+    return e
+
+
+def lbm_engine_add(e, h, steps: int) -> int:
+    slot = np.zeros(1, dtype=np.int32)
+    _echeck(load().lbm_engine_add(e, h, steps, _ptr(slot)), e)
+    return int(slot[0])
+
+
+def lbm_engine_remove(e, slot: int) -> None:
+    _echeck(load().lbm_engine_remove(e, slot), e)
+
+
+def lbm_engine_step(e, n: int) -> None:
+    _echeck(load().lbm_engine_step(e, n), e)
+
+
+def lbm_engine_status(e, max_slots: int) -> np.ndarray:
+    out = np.zeros(max_slots, dtype=np.int32)
+    _echeck(load().lbm_engine_status(e, _ptr(out)), e)
+    return out
+
+
+def lbm_engine_set_tiling(e, block: int, groups: int, schedule: int) -> None:
+    _echeck(load().lbm_engine_set_tiling(e, block, groups, schedule), e)
+
+
+def lbm_engine_get_tiling(e):
+    out = np.zeros(3, dtype=np.int32)
+    _echeck(load().lbm_engine_get_tiling(e, _ptr(out)), e)
+    return tuple(int(v) for v in out)
+
+
+def lbm_engine_tune(e, reps: int):
+    out = np.zeros(3, dtype=np.int32)
+    ms = np.zeros(1, dtype=np.float64)
+    _echeck(load().lbm_engine_tune(e, reps, _ptr(out), _ptr(ms)), e)
+    return tuple(int(v) for v in out), float(ms[0])
+
+
+def lbm_engine_destroy(e) -> None:
+    load().lbm_engine_destroy(e)
+
+
 class Lattice:
     """A lattice bound to device memory owned by a torch uint8 tensor.
 
@@ -294,6 +368,59 @@ class Lattice:
         if getattr(self, "h", None) is not None:
             lbm_destroy(self.h)
             self.h = None
+        self.mem = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Engine:
+    """An ensemble engine on a torch-owned slot table (one C-ABI call per
+    operation)."""
+
+    def __init__(self, max_slots: int, device=None, stream=None):
+        import torch
+        self.max_slots = max_slots
+        self.device = torch.device(device if device is not None else "cuda")
+        n = lbm_engine_required_bytes(max_slots)
+        self.mem = torch.empty(n, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.e = lbm_engine_create(max_slots, self.mem.data_ptr(), n, self.stream.cuda_stream)
+
+    def add(self, lat: "Lattice", steps: int) -> int:
+        return lbm_engine_add(self.e, lat.h, steps)
+
+    def remove(self, slot: int) -> None:
+        lbm_engine_remove(self.e, slot)
+
+    def step(self, n: int = 1) -> None:
+        lbm_engine_step(self.e, n)
+
+    def status(self) -> np.ndarray:
+        return lbm_engine_status(self.e, self.max_slots)
+
+    def tune(self, reps: int = 3):
+        return lbm_engine_tune(self.e, reps)
+
+    def set_tiling(self, block: int, groups: int, schedule: int) -> None:
+        lbm_engine_set_tiling(self.e, block, groups, schedule)
+
+    def tiling(self):
+        return lbm_engine_get_tiling(self.e)
+
+    def close(self) -> None:
+        if getattr(self, "e", None) is not None:
+            lbm_engine_destroy(self.e)
+            self.e = None
         self.mem = None
 
     def __enter__(self):

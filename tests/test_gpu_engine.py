@@ -1,0 +1,167 @@
+"""Ensemble engine: many lattices stepped by one persistent launch per step.
+
+Each lattice in the mix must end bit-identical to the same lattice stepped
+alone with lbm_step (the engine runs the fused kernel's arithmetic; only
+the tile order and the periodic wrap differ), whatever the tiling, the
+schedule, the storage mix and the order in which lattices join and leave.
+One FP64 member is also checked against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import FP64_TOL, err_metric, need_gpu, note
+from paper_1703_00185_amd import inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+# (lx, ly, storage, steps, tau, gravity, t_bottom, t_top)
+MIX = [
+    (64, 128, lbm.LBM_FP64, 9, 0.8, 1e-4, 1.05, 0.95),
+    (37, 70, lbm.LBM_FP32, 5, 0.7, 3e-4, 1.1, 0.9),
+    (130, 257, lbm.LBM_FP64, 12, 1.2, 1e-4, 1.02, 0.98),
+    (3, 6, lbm.LBM_FP64, 4, 0.8, 0.0, 1.0, 1.0),
+    (9, 1100, lbm.LBM_FP32, 7, 0.9, 2e-4, 1.08, 0.93),
+    (16, 32, lbm.LBM_FP64, 0, 0.8, 1e-4, 1.05, 0.95),
+    (256, 64, lbm.LBM_FP32, 3, 0.65, 1e-4, 1.15, 0.85),
+]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _lattice(spec, seed):
+    lx, ly, storage, _, tau, grav, tb, tt = spec
+    ns = inputs.rt_config(lx, ly, tau=tau, gravity=grav, t_bottom=tb, t_top=tt)
+    cfg = lbm.config_from(ns, storage=storage)
+    lat = lbm.Lattice(cfg)
+    lat.init_rt(inputs.rt_perturbation(seed, ly))
+    return lat, ns
+
+
+def _alone(spec, seed, steps):
+    lat, _ = _lattice(spec, seed)
+    with lat:
+        lat.step(steps)
+        return lat.get()
+
+
+def _run_engine(mix, tiling=None):
+    lats = [_lattice(spec, i)[0] for i, spec in enumerate(mix)]
+    eng = lbm.Engine(max_slots=16)
+    try:
+        if tiling:
+            eng.set_tiling(*tiling)
+        slots = [eng.add(lat, spec[3]) for lat, spec in zip(lats, mix)]
+        eng.step(max(spec[3] for spec in mix) + 2)  # extra steps: finished lattices stay put
+        left = eng.status()
+        assert all(left[s] == 0 for s in slots)
+        out = [lat.get() for lat in lats]
+    finally:
+        eng.close()
+        for lat in lats:
+            lat.close()
+    return out
+
+
+@pytest.mark.parametrize("tiling", [None, (64, 3, 0), (128, 1024, 1), (512, 7, 0), (256, 2048, 1)])
+def test_mix_equals_each_lattice_alone(tiling):
+    got = _run_engine(MIX, tiling)
+    for i, spec in enumerate(MIX):
+        want = _alone(spec, i, spec[3])
+        assert np.array_equal(got[i], want), (i, spec, tiling)
+
+
+def test_engine_member_matches_oracle():
+    spec = MIX[0]
+    got = _run_engine([spec, MIX[1], MIX[2]])[0]
+    lx, ly, _, steps, tau, grav, tb, tt = spec
+    ns = inputs.rt_config(lx, ly, tau=tau, gravity=grav, t_bottom=tb, t_top=tt)
+    f = oracle.run(oracle.init_rt(lx, ly, ns, inputs.rt_perturbation(0, ly)), ns, steps)
+    assert err_metric(got, f) < FP64_TOL
+
+
+def test_join_and_leave_mid_run():
+    """Continuous batching: lattices join and leave between engine steps."""
+    a_spec, b_spec, c_spec = MIX[0], MIX[1], MIX[2]
+    a, _ = _lattice(a_spec, 0)
+    b, _ = _lattice(b_spec, 1)
+    c, _ = _lattice(c_spec, 2)
+    eng = lbm.Engine(max_slots=4)
+    try:
+        sa = eng.add(a, 10)
+        eng.step(3)
+        sb = eng.add(b, 6)
+        eng.step(2)
+        eng.remove(sa)             # a leaves after 5 of its 10 steps
+        sc = eng.add(c, 4)
+        eng.step(8)
+        left = eng.status()
+        assert left[sa] == -1 and left[sb] == 0 and left[sc] == 0
+        got_a, got_b, got_c = a.get(), b.get(), c.get()
+        with pytest.raises(lbm.LbmError) as ei:
+            b.step(1)              # stepping an engine member directly is refused
+        assert ei.value.status == lbm.LBM_ESTATE
+        a.step(1)                  # a left the engine: it steps on its own again
+        got_a6 = a.get()
+    finally:
+        eng.close()
+        for lat in (a, b, c):
+            lat.close()
+    assert np.array_equal(got_a, _alone(a_spec, 0, 5))
+    assert np.array_equal(got_a6, _alone(a_spec, 0, 6))
+    assert np.array_equal(got_b, _alone(b_spec, 1, 6))
+    assert np.array_equal(got_c, _alone(c_spec, 2, 4))
+
+
+def test_autotune_leaves_state_unchanged_and_picks_a_valid_tiling():
+    lats = [_lattice(spec, i)[0] for i, spec in enumerate(MIX[:5])]
+    eng = lbm.Engine(max_slots=8)
+    try:
+        for lat, spec in zip(lats, MIX[:5]):
+            eng.add(lat, spec[3])
+        before = [lat.get() for lat in lats]
+        (block, groups, sched), ms = eng.tune(reps=2)
+        note(f"engine tune: block {block}, groups {groups}, schedule {sched}, {ms:.3f} ms/step")
+        assert block in (64, 128, 256, 512) and groups > 0 and sched in (0, 1) and ms > 0
+        assert eng.tiling() == (block, groups, sched)
+        after = [lat.get() for lat in lats]
+        assert all(np.array_equal(x, y) for x, y in zip(before, after))
+        eng.step(20)
+        eng.status()
+        got = [lat.get() for lat in lats]
+    finally:
+        eng.close()
+        for lat in lats:
+            lat.close()
+    for i, spec in enumerate(MIX[:5]):
+        assert np.array_equal(got[i], _alone(spec, i, spec[3]))
+
+
+def test_engine_argument_checks():
+    lat, _ = _lattice(MIX[0], 0)
+    f16 = lbm.Lattice(lbm.config_from(inputs.rt_config(16, 32), storage=lbm.LBM_FP16DEV))
+    eng = lbm.Engine(max_slots=1)
+    try:
+        with pytest.raises(lbm.LbmError):
+            eng.add(f16, 3)                      # deviation storage is not engine-stepped
+        s = eng.add(lat, 2)
+        with pytest.raises(lbm.LbmError):
+            eng.add(lat, 2)                      # already in
+        other, _ = _lattice(MIX[1], 1)
+        with other:
+            with pytest.raises(lbm.LbmError) as ei:
+                eng.add(other, 2)                # no free slot
+            assert ei.value.status == lbm.LBM_ENOMEM
+        with pytest.raises(lbm.LbmError):
+            eng.set_tiling(96, 10, 0)
+        with pytest.raises(lbm.LbmError):
+            eng.remove(s + 1)
+        eng.step(5)
+        assert eng.status()[s] == 0
+    finally:
+        eng.close()
+        lat.close()
+        f16.close()
