@@ -122,7 +122,8 @@ def kernel_bandwidth(kernels: dict, sites: int, lx: int, ly: int, elem_bytes: in
     per_site = 2 * 37 * elem_bytes
     algo = {"fused": per_site * sites, "propagate": per_site * sites,
             "collide": per_site * sites, "bc": per_site * 6 * lx,
-            "pbc": 2 * 52 * ly * elem_bytes}
+            "pbc": 2 * 52 * ly * elem_bytes, "fused_bulk": per_site * (lx - 6) * ly,
+            "fused_border": per_site * 6 * ly}
     for name, k in kernels.items():
         k["algorithmic_bytes"] = algo[name]
         k["gbs"] = algo[name] / (k["avg_ms"] * 1e-3) / 1e9
@@ -225,6 +226,12 @@ def main() -> int:
         log(f"{name} storage: {reduced[name]['mlups']:.1f} MLUPS, "
             f"fused kernel {k3['fused']['gbs']:.0f} GB/s")
 
+    log(f"region path {lx}x{ly}: {args.warmup} warmup + {args.steps} timed steps")
+    w4, k4, _, _ = time_path(lbm, ns, rt, lbm.LBM_PATH_REGIONS, args.steps, args.warmup, extra)
+    regions = {"mlups": sites * args.steps / w4 / 1e6, "ms_per_step": w4 / args.steps * 1e3,
+               "kernels": kernel_bandwidth(k4, sites, lx, ly)}
+    log(f"regions: {regions['mlups']:.1f} MLUPS")
+
     fk = kern["fused"]
     traffic = measured_traffic(lx, ly)
     roofline = {"bound": "hbm", "achieved": fk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -247,7 +254,7 @@ def main() -> int:
                        "nx": layout[0], "ny_pitch": layout[1], "plane_elems": layout[2],
                        "block": args.block or 256}},
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kern, "separate": separate,
-        "bandwidth_probe": copy, "reduced_storage": reduced,
+        "bandwidth_probe": copy, "reduced_storage": reduced, "regions": regions,
         "paper_equivalent_gflops": 6472 * sites * args.steps / wall / 1e9,
     }
     print(json.dumps(out), flush=True)

@@ -66,7 +66,12 @@ typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16DEV = 2 } lbm_storage;
 /* Kernel sequence of lbm_step (Sec. 2 kernel list; fusion as in Sec. 5). */
 typedef enum {
   LBM_PATH_SEPARATE = 0, /* pbc, propagate, bc, collide: four kernels */
-  LBM_PATH_FUSED = 1     /* pbc, then one kernel doing propagate+bc+collide */
+  LBM_PATH_FUSED = 1,    /* pbc, then one kernel doing propagate+bc+collide */
+  LBM_PATH_REGIONS = 2   /* region split (Sec. 5, 1-D tiling): the fused
+                            kernel on the bulk columns 3..Lx-4 runs while
+                            pbc refreshes the halos on a second stream, then
+                            the 3 + 3 border columns run; same results as
+                            LBM_PATH_FUSED bit for bit */
 } lbm_path;
 
 /* Single phases for lbm_run_phase and the timing counters. */
@@ -76,7 +81,9 @@ typedef enum {
   LBM_PHASE_BC = 2,        /* thermal walls on the 6 wall rows (in place) */
   LBM_PHASE_COLLIDE = 3,   /* collision into the other buffer */
   LBM_PHASE_FUSED = 4,     /* propagate + bc + collide into the other buffer */
-  LBM_NPHASES = 5
+  LBM_PHASE_FUSED_BULK = 5,   /* timing only: region path, bulk columns */
+  LBM_PHASE_FUSED_BORDER = 6, /* timing only: region path, border columns */
+  LBM_NPHASES = 7
 } lbm_phase;
 
 typedef struct {
@@ -140,7 +147,8 @@ int lbm_step(lbm_handle *h, int32_t n);
 
 /* Run one phase on the current state (test and profiling hook): PBC and BC
  * work in place, PROPAGATE, COLLIDE and FUSED write the other copy, which
- * then becomes current.  Asynchronous.  Errors: EINVAL, ESTATE, EDEVICE. */
+ * then becomes current.  Phases 0..4 only.  Asynchronous.  Errors: EINVAL,
+ * ESTATE, EDEVICE. */
 int lbm_run_phase(lbm_handle *h, int32_t phase);
 
 /* Per-site moments of the current populations (Sec. 2, under Eq. 6):

@@ -26,6 +26,10 @@ struct lbm_handle {
   d2q37::CollideParams cp{};
   d2q37::WallParams wp{};
   std::string err;
+  // region path: a second stream for pbc and the events that order it
+  hipStream_t side = nullptr;
+  hipEvent_t ev_ready = nullptr;
+  hipEvent_t ev_halo = nullptr;
   // per-launch timing
   bool timing = false;
   std::vector<hipEvent_t> events;
@@ -33,7 +37,7 @@ struct lbm_handle {
   struct Rec {
     int phase;
     size_t ev;
-  };
+  };  // events ev, ev + 1 recorded on the launch's stream
   std::vector<Rec> recs;
 };
 

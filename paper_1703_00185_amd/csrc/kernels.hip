@@ -24,11 +24,16 @@ namespace {
 // ---------------------------------------------------------------------------
 
 // Site of this lane: column x (physical), row y, first row of its wavefront.
+// The grid covers cols.na columns from cols.xa, then columns from cols.xb
+// (two ranges, so that the two border strips of a region split are one
+// launch); a full-lattice launch uses xa = 0, na = lx.
 template <int BLOCK>
-__device__ __forceinline__ void lane_site(const Geometry& g, int& x, int& y, int& ywave) {
+__device__ __forceinline__ void lane_site(const Geometry& g, const ColumnSet& cols, int& x, int& y,
+                                          int& ywave) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  x = tile / g.ny_blocks;
-  const int yb = tile - x * g.ny_blocks;
+  const int c = tile / g.ny_blocks;
+  x = c < cols.na ? cols.xa + c : cols.xb + (c - cols.na);
+  const int yb = tile - c * g.ny_blocks;
   y = yb * BLOCK + threadIdx.x;
   ywave = yb * BLOCK + (threadIdx.x & ~(WAVE - 1));
 }
@@ -149,7 +154,7 @@ __global__ void __launch_bounds__(BLOCK) propagate_kernel(const typename C::S* _
                                                           typename C::S* __restrict__ dst, Geometry g) {
   const C cd{g.ref, g.inv_ref};
   int x, y, ywave;
-  lane_site<BLOCK>(g, x, y, ywave);
+  lane_site<BLOCK>(g, ColumnSet{0, g.lx, 0}, x, y, ywave);
   double f[NPOP];
   if (interior_wave(g, ywave)) {
     gather_interior(g, cd, src, x, y, f);
@@ -182,7 +187,7 @@ __global__ void __launch_bounds__(BLOCK) collide_kernel(const typename C::S* __r
                                                         CollideParams c) {
   const C cd{g.ref, g.inv_ref};
   int x, y, ywave;
-  lane_site<BLOCK>(g, x, y, ywave);
+  lane_site<BLOCK>(g, ColumnSet{0, g.lx, 0}, x, y, ywave);
   if (y >= g.ly) return;
   double f[NPOP];
   load_site(g, cd, src, x, y, f);
@@ -196,10 +201,10 @@ __global__ void __launch_bounds__(BLOCK) collide_kernel(const typename C::S* __r
 template <class C, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) fused_kernel(const typename C::S* __restrict__ src,
                                                       typename C::S* __restrict__ dst, Geometry g,
-                                                      CollideParams c, WallParams w) {
+                                                      CollideParams c, WallParams w, ColumnSet cols) {
   const C cd{g.ref, g.inv_ref};
   int x, y, ywave;
-  lane_site<BLOCK>(g, x, y, ywave);
+  lane_site<BLOCK>(g, cols, x, y, ywave);
   double f[NPOP];
   if (interior_wave(g, ywave)) {
     gather_interior(g, cd, src, x, y, f);
@@ -484,10 +489,14 @@ hipError_t launch_collide(const Geometry& g, const void* src, void* dst, const C
 }
 
 hipError_t launch_fused(const Geometry& g, const void* src, void* dst, const CollideParams& c,
-                        const WallParams& w, hipStream_t s) {
+                        const WallParams& w, hipStream_t s, const ColumnSet* cols) {
+  const ColumnSet all{0, g.lx, 0};
+  const ColumnSet cs = cols ? *cols : all;
+  const int ncols = cs.na + (cols ? cs.nb : 0);
+  if (ncols <= 0) return hipSuccess;
   (void)hipGetLastError();
-  D2Q37_DISPATCH(g, hipLaunchKernelGGL((fused_kernel<C, BS>), dim3(g.lx * g.ny_blocks), dim3(BS), 0,
-                                       s, static_cast<const S*>(src), static_cast<S*>(dst), g, c, w));
+  D2Q37_DISPATCH(g, hipLaunchKernelGGL((fused_kernel<C, BS>), dim3(ncols * g.ny_blocks), dim3(BS), 0,
+                                       s, static_cast<const S*>(src), static_cast<S*>(dst), g, c, w, cs));
   return hipGetLastError();
 }
 

@@ -41,6 +41,13 @@ struct WallParams {
   double kt[NPOP];
 };
 
+// Columns covered by a lattice launch: na columns from xa, then nb
+// columns from xb (nb is used by the host only, to size the grid).
+struct ColumnSet {
+  int xa, na, xb;
+  int nb = 0;
+};
+
 // Rayleigh-Taylor initial state parameters.
 constexpr int MAX_MODES = 32;
 struct RtParams {
@@ -63,8 +70,9 @@ hipError_t launch_propagate(const Geometry& g, const void* src, void* dst, hipSt
 hipError_t launch_bc(const Geometry& g, void* f, const WallParams& w, hipStream_t s);
 hipError_t launch_collide(const Geometry& g, const void* src, void* dst, const CollideParams& c,
                           hipStream_t s);
+// cols = nullptr: every column; else the two column ranges of *cols.
 hipError_t launch_fused(const Geometry& g, const void* src, void* dst, const CollideParams& c,
-                        const WallParams& w, hipStream_t s);
+                        const WallParams& w, hipStream_t s, const ColumnSet* cols = nullptr);
 hipError_t launch_moments(const Geometry& g, const void* f, double* out, hipStream_t s);
 hipError_t launch_conservation(const Geometry& g, const void* f, double* partials, double* result,
                                hipStream_t s);

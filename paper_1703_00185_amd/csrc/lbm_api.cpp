@@ -42,8 +42,8 @@ int make_layout(const lbm_config* c, Layout* out, std::string* why) {
     return *why = "wall temperatures must be finite and > 0", LBM_EINVAL;
   if (c->storage != LBM_FP64 && c->storage != LBM_FP32 && c->storage != LBM_FP16DEV)
     return *why = "storage must be LBM_FP64, LBM_FP32 or LBM_FP16DEV", LBM_EINVAL;
-  if (c->path != LBM_PATH_SEPARATE && c->path != LBM_PATH_FUSED)
-    return *why = "path must be LBM_PATH_SEPARATE or LBM_PATH_FUSED", LBM_EINVAL;
+  if (c->path != LBM_PATH_SEPARATE && c->path != LBM_PATH_FUSED && c->path != LBM_PATH_REGIONS)
+    return *why = "path must be LBM_PATH_SEPARATE, LBM_PATH_FUSED or LBM_PATH_REGIONS", LBM_EINVAL;
   const int block = c->block == 0 ? 256 : c->block;
   if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
     return *why = "block must be 0, 64, 128, 256, 512 or 1024", LBM_EINVAL;
@@ -81,8 +81,10 @@ size_t plane_col0(const Geometry& g, int l) {
 }
 
 // Launch with optional timing events around it.
+int run_phase(lbm_handle* h, int phase);
+
 template <class F>
-int timed(lbm_handle* h, int phase, F&& launch) {
+int timed_on(lbm_handle* h, int phase, hipStream_t stream, F&& launch) {
   size_t ev = 0;
   if (h->timing) {
     if (h->ev_used + 2 > h->events.size()) {
@@ -94,13 +96,51 @@ int timed(lbm_handle* h, int phase, F&& launch) {
     }
     ev = h->ev_used;
     h->ev_used += 2;
-    LBM_HIP(h, hipEventRecord(h->events[ev], h->stream));
+    LBM_HIP(h, hipEventRecord(h->events[ev], stream));
   }
   LBM_HIP(h, launch());
   if (h->timing) {
-    LBM_HIP(h, hipEventRecord(h->events[ev + 1], h->stream));
+    LBM_HIP(h, hipEventRecord(h->events[ev + 1], stream));
     h->recs.push_back({phase, ev});
   }
+  return LBM_OK;
+}
+
+template <class F>
+int timed(lbm_handle* h, int phase, F&& launch) {
+  return timed_on(h, phase, h->stream, launch);
+}
+
+// One step of the region path: pbc on the side stream, overlapped with the
+// fused kernel on the bulk columns (which read no halo), then the border
+// columns once the halos are in place.  Lattices narrower than 7 columns
+// have no bulk and take the plain fused step.
+int region_step(lbm_handle* h) {
+  const Geometry& g = h->geo;
+  if (g.lx < 7) {
+    int rc = run_phase(h, LBM_PHASE_PBC);
+    return rc == LBM_OK ? run_phase(h, LBM_PHASE_FUSED) : rc;
+  }
+  if (!h->side) {
+    LBM_HIP(h, hipStreamCreate(&h->side));
+    LBM_HIP(h, hipEventCreateWithFlags(&h->ev_ready, hipEventDisableTiming));
+    LBM_HIP(h, hipEventCreateWithFlags(&h->ev_halo, hipEventDisableTiming));
+  }
+  LBM_HIP(h, hipEventRecord(h->ev_ready, h->stream));
+  LBM_HIP(h, hipStreamWaitEvent(h->side, h->ev_ready, 0));
+  int rc = timed_on(h, LBM_PHASE_PBC, h->side, [&] { return launch_pbc(g, current(h), h->side); });
+  if (rc != LBM_OK) return rc;
+  LBM_HIP(h, hipEventRecord(h->ev_halo, h->side));
+  ColumnSet bulk{HALO, g.lx - 2 * HALO, 0};
+  rc = timed(h, LBM_PHASE_FUSED_BULK,
+             [&] { return launch_fused(g, current(h), other(h), h->cp, h->wp, h->stream, &bulk); });
+  if (rc != LBM_OK) return rc;
+  LBM_HIP(h, hipStreamWaitEvent(h->stream, h->ev_halo, 0));
+  ColumnSet border{0, HALO, g.lx - HALO, HALO};
+  rc = timed(h, LBM_PHASE_FUSED_BORDER,
+             [&] { return launch_fused(g, current(h), other(h), h->cp, h->wp, h->stream, &border); });
+  if (rc != LBM_OK) return rc;
+  h->cur ^= 1;
   return LBM_OK;
 }
 
@@ -261,6 +301,11 @@ int lbm_step(lbm_handle* h, int32_t n) {
   if (h->engine) return fail(h, LBM_ESTATE, "lattice is stepped by an engine (remove it first)");
   DeviceGuard dg(h->device);
   for (int32_t i = 0; i < n; ++i) {
+    if (h->cfg.path == LBM_PATH_REGIONS) {
+      const int rc = region_step(h);
+      if (rc != LBM_OK) return rc;
+      continue;
+    }
     int rc = run_phase(h, LBM_PHASE_PBC);
     if (rc == LBM_OK) {
       if (h->cfg.path == LBM_PATH_FUSED) {
@@ -278,7 +323,7 @@ int lbm_step(lbm_handle* h, int32_t n) {
 
 int lbm_run_phase(lbm_handle* h, int32_t phase) {
   if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
-  if (phase < 0 || phase >= LBM_NPHASES) return fail(h, LBM_EINVAL, "unknown phase");
+  if (phase < 0 || phase > LBM_PHASE_FUSED) return fail(h, LBM_EINVAL, "unknown phase");
   if (!h->ready) return fail(h, LBM_ESTATE, "lattice not initialised");
   if (h->engine) return fail(h, LBM_ESTATE, "lattice is stepped by an engine (remove it first)");
   DeviceGuard dg(h->device);
@@ -436,6 +481,7 @@ int lbm_read_timing(lbm_handle* h, double ms[LBM_NPHASES], int64_t count[LBM_NPH
   if (!ms || !count) return fail(h, LBM_EINVAL, "ms/count are NULL");
   DeviceGuard dg(h->device);
   LBM_HIP(h, hipStreamSynchronize(h->stream));
+  if (h->side) LBM_HIP(h, hipStreamSynchronize(h->side));
   for (int p = 0; p < LBM_NPHASES; ++p) {
     ms[p] = 0.0;
     count[p] = 0;
@@ -502,6 +548,12 @@ void lbm_destroy(lbm_handle* h) {
     DeviceGuard dg(h->device);
     (void)hipStreamSynchronize(h->stream);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    if (h->side) {
+      (void)hipStreamSynchronize(h->side);
+      (void)hipStreamDestroy(h->side);
+      (void)hipEventDestroy(h->ev_ready);
+      (void)hipEventDestroy(h->ev_halo);
+    }
   }
   delete h;
 }

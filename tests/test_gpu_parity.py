@@ -248,7 +248,7 @@ def test_timing_counters_and_state_errors():
         lat.step(3)
         ms, cnt = lbm.lbm_read_timing(lat.h)
         lbm.lbm_set_timing(lat.h, False)
-    assert cnt.tolist() == [3, 0, 0, 0, 3]
+    assert cnt.tolist() == [3, 0, 0, 0, 3, 0, 0]
     assert ms[0] > 0 and ms[4] > 0
 
 

@@ -1,0 +1,43 @@
+"""Region-split step (bulk columns overlapped with pbc on a second stream,
+then the border columns): bit-identical to the fused step, and within the
+FP64 tolerance of the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import FP64_TOL, err_metric, lattice, need_gpu
+from paper_1703_00185_amd import inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+@pytest.mark.parametrize("storage", [lbm.LBM_FP64, lbm.LBM_FP32])
+@pytest.mark.parametrize("lx,ly", [(3, 6), (6, 12), (7, 20), (37, 70), (64, 128), (130, 257)])
+def test_regions_equal_fused(lx, ly, storage):
+    ns = inputs.rt_config(lx, ly)
+    rt = inputs.rt_perturbation(2, ly)
+    out = []
+    for path in (lbm.LBM_PATH_FUSED, lbm.LBM_PATH_REGIONS):
+        with lattice(ns, path=path, storage=storage) as lat:
+            lat.init_rt(rt)
+            lat.step(9)
+            out.append(lat.get())
+    assert np.array_equal(out[0], out[1])
+
+
+def test_regions_match_oracle_and_time_both_parts():
+    ns = inputs.rt_config(64, 128)
+    f0 = oracle.init_rt(64, 128, ns, inputs.rt_perturbation(3, 128))
+    with lattice(ns, path=lbm.LBM_PATH_REGIONS) as lat:
+        lat.set(f0)
+        lbm.lbm_set_timing(lat.h, True)
+        lat.step(4)
+        ms, cnt = lbm.lbm_read_timing(lat.h)
+        got = lat.get()
+    assert cnt.tolist() == [4, 0, 0, 0, 0, 4, 4]
+    assert err_metric(got, oracle.run(f0, ns, 4)) < FP64_TOL
