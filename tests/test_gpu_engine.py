@@ -99,7 +99,9 @@ def test_join_and_leave_mid_run():
         sc = eng.add(c, 4)
         eng.step(8)
         left = eng.status()
-        assert left[sa] == -1 and left[sb] == 0 and left[sc] == 0
+        assert sc == sa                    # the freed slot is reused
+        assert left[sb] == 0 and left[sc] == 0
+        assert all(left[s] == -1 for s in range(4) if s not in (sb, sc))
         got_a, got_b, got_c = a.get(), b.get(), c.get()
         with pytest.raises(lbm.LbmError) as ei:
             b.step(1)              # stepping an engine member directly is refused
