@@ -248,7 +248,7 @@ typedef enum { LBM_SCHED_CHUNKED = 0, LBM_SCHED_STRIDED = 1 } lbm_schedule;
 size_t lbm_engine_required_bytes(int32_t max_slots);
 
 /* Create an engine on caller memory (256-byte aligned) and stream.
- * Default tiling: block 256, 4 work-groups per compute unit, CHUNKED.
+ * Default tiling: block 256, 256 work-groups per compute unit, STRIDED.
  * Errors: EINVAL, ENOMEM (block too small / misaligned), EDEVICE. */
 int lbm_engine_create(int32_t max_slots, void *dev_mem, size_t dev_bytes, void *stream,
                       lbm_engine **out);
@@ -279,7 +279,7 @@ int lbm_engine_get_tiling(const lbm_engine *e, int32_t out[3]);
 /* Autotune the tiling on the current lattices: times `reps` step launches
  * (without advancing any lattice: each launch rewrites the idle buffer from
  * the current one) for every block in {64,128,256,512}, groups in
- * {1,2,4,8,16} x compute units and both schedules; keeps the fastest.
+ * {2,4,...,256} x compute units and both schedules; keeps the fastest.
  * out[3] = chosen (block, groups, schedule), *best_ms = its time per step
  * (either may be NULL).  Errors: ESTATE (no active lattice), EDEVICE. */
 int lbm_engine_tune(lbm_engine *e, int32_t reps, int32_t out[3], double *best_ms);

@@ -238,7 +238,10 @@ int lbm_engine_create(int32_t max_slots, void* dev_mem, size_t dev_bytes, void* 
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, e->device) != hipSuccess || cus <= 0)
     cus = 256;
   e->cus = cus;
-  e->groups = 4 * cus;
+  // default: a large strided grid (about one tile per work-group on big
+  // lattices), which measured faster than a persistent chunked grid
+  e->groups = 256 * cus;
+  e->schedule = SCHED_STRIDED;
   // every slot starts free: zeroed descriptors (steps_left 0) and status
   std::vector<SlotDesc> zero(max_slots, SlotDesc{});
   std::vector<int> zst(2 * static_cast<size_t>(max_slots), 0);
@@ -385,7 +388,7 @@ int lbm_engine_tune(lbm_engine* e, int32_t reps, int32_t out[3], double* best_ms
   int best[3] = {e->block, e->groups, e->schedule};
   float best_t = 1e30f;
   const int blocks[] = {64, 128, 256, 512};
-  const int per_cu[] = {1, 2, 4, 8, 16};
+  const int per_cu[] = {2, 4, 8, 16, 32, 64, 128, 256};
   for (int blk : blocks) {
     e->block = blk;
     rc = upload_slots(e);
