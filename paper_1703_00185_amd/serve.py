@@ -82,8 +82,14 @@ class Server:
         done = {}                   # rid -> completion time
         site_steps = 0
         t0 = time.perf_counter()
+        next_report = 10.0
         while pending or queue or active:
             now = time.perf_counter() - t0
+            if now >= next_report:
+                print(f"[serve] t={now:.0f} s: {len(done)} done, {len(active)} active, "
+                      f"{len(queue)} queued, {self.used / 2**30:.1f} GiB in use",
+                      file=sys.stderr, flush=True)
+                next_report = now + 10.0
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
             while queue and len(active) < self.max_slots:
