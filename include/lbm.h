@@ -145,6 +145,14 @@ int lbm_init_rt(lbm_handle *h, const lbm_rt_params *rt);
  * Asynchronous.  Errors: EINVAL (n < 0), ESTATE (no state yet), EDEVICE. */
 int lbm_step(lbm_handle *h, int32_t n);
 
+/* Same steps as lbm_step, replayed from a HIP graph: the first call for a
+ * given n and current buffer captures the n steps from this handle's
+ * stream (launches only, nothing else may be enqueued on that stream
+ * meanwhile) and keeps the instantiated graph until lbm_destroy; later
+ * calls launch it.  Removes the per-launch host cost of short steps.
+ * Asynchronous.  Errors: EINVAL (n < 0, timing enabled), ESTATE, EDEVICE. */
+int lbm_step_captured(lbm_handle *h, int32_t n);
+
 /* Run one phase on the current state (test and profiling hook): PBC and BC
  * work in place, PROPAGATE, COLLIDE and FUSED write the other copy, which
  * then becomes current.  Phases 0..4 only.  Asynchronous.  Errors: EINVAL,

@@ -30,6 +30,13 @@ struct lbm_handle {
   hipStream_t side = nullptr;
   hipEvent_t ev_ready = nullptr;
   hipEvent_t ev_halo = nullptr;
+  // captured step sequences: (n, starting buffer) -> instantiated graph
+  struct Captured {
+    int n, cur;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<Captured> captured;
   // per-launch timing
   bool timing = false;
   std::vector<hipEvent_t> events;

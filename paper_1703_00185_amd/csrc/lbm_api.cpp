@@ -321,6 +321,47 @@ int lbm_step(lbm_handle* h, int32_t n) {
   return LBM_OK;
 }
 
+int lbm_step_captured(lbm_handle* h, int32_t n) {
+  if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
+  if (n < 0) return fail(h, LBM_EINVAL, "n must be >= 0");
+  if (!h->ready) return fail(h, LBM_ESTATE, "lattice not initialised");
+  if (h->engine) return fail(h, LBM_ESTATE, "lattice is stepped by an engine (remove it first)");
+  if (h->timing) return fail(h, LBM_EINVAL, "timing must be off for captured steps");
+  if (n == 0) return LBM_OK;
+  DeviceGuard dg(h->device);
+  const int start = h->cur;
+  hipGraphExec_t exec = nullptr;
+  for (const auto& c : h->captured)
+    if (c.n == n && c.cur == start) exec = c.exec;
+  if (!exec) {
+    if (h->cfg.path == LBM_PATH_REGIONS && !h->side) {
+      // create the side stream outside the capture
+      LBM_HIP(h, hipStreamCreate(&h->side));
+      LBM_HIP(h, hipEventCreateWithFlags(&h->ev_ready, hipEventDisableTiming));
+      LBM_HIP(h, hipEventCreateWithFlags(&h->ev_halo, hipEventDisableTiming));
+    }
+    LBM_HIP(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    const int rc = lbm_step(h, n);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->stream, &graph);
+    h->cur = start;  // the capture only recorded the steps
+    if (rc != LBM_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(h, LBM_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return fail(h, LBM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+    h->captured.push_back({n, start, graph, exec});
+  }
+  LBM_HIP(h, hipGraphLaunch(exec, h->stream));
+  h->cur = start ^ (n & 1);
+  return LBM_OK;
+}
+
 int lbm_run_phase(lbm_handle* h, int32_t phase) {
   if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
   if (phase < 0 || phase > LBM_PHASE_FUSED) return fail(h, LBM_EINVAL, "unknown phase");
@@ -548,6 +589,10 @@ void lbm_destroy(lbm_handle* h) {
     DeviceGuard dg(h->device);
     (void)hipStreamSynchronize(h->stream);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    for (auto& c : h->captured) {
+      (void)hipGraphExecDestroy(c.exec);
+      (void)hipGraphDestroy(c.graph);
+    }
     if (h->side) {
       (void)hipStreamSynchronize(h->side);
       (void)hipStreamDestroy(h->side);

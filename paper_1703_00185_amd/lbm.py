@@ -69,6 +69,7 @@ def load():
         "lbm_set_stream": (c_int, [H, c_void_p]),
         "lbm_init_rt": (c_int, [H, POINTER(lbm_rt_params)]),
         "lbm_step": (c_int, [H, c_int32]),
+        "lbm_step_captured": (c_int, [H, c_int32]),
         "lbm_run_phase": (c_int, [H, c_int32]),
         "lbm_moments": (c_int, [H, c_void_p, c_void_p, c_void_p, c_void_p]),
         "lbm_conservation": (c_int, [H, c_void_p]),
@@ -158,6 +159,10 @@ def lbm_init_rt(h, width: float, y_center: float, amps, phases) -> None:
 
 def lbm_step(h, n: int) -> None:
     _check(load().lbm_step(h, n), h)
+
+
+def lbm_step_captured(h, n: int) -> None:
+    _check(load().lbm_step_captured(h, n), h)
 
 
 def lbm_run_phase(h, phase: int) -> None:
@@ -342,6 +347,9 @@ class Lattice:
 
     def step(self, n: int = 1) -> None:
         lbm_step(self.h, n)
+
+    def step_captured(self, n: int = 1) -> None:
+        lbm_step_captured(self.h, n)
 
     def run_phase(self, phase: int) -> None:
         lbm_run_phase(self.h, phase)

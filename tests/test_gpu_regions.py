@@ -41,3 +41,19 @@ def test_regions_match_oracle_and_time_both_parts():
         got = lat.get()
     assert cnt.tolist() == [4, 0, 0, 0, 0, 4, 4]
     assert err_metric(got, oracle.run(f0, ns, 4)) < FP64_TOL
+
+
+@pytest.mark.parametrize("path", [lbm.LBM_PATH_SEPARATE, lbm.LBM_PATH_FUSED, lbm.LBM_PATH_REGIONS])
+def test_captured_steps_equal_plain_steps(path):
+    """Graph-replayed steps (odd and even counts, both buffer parities,
+    replayed several times with eager work in between) equal plain steps."""
+    ns = inputs.rt_config(64, 128)
+    rt = inputs.rt_perturbation(1, 128)
+    with lattice(ns, path=path) as a, lattice(ns, path=path) as b:
+        a.init_rt(rt)
+        b.init_rt(rt)
+        for n in (3, 4, 3, 3, 4, 1):
+            a.step(n)
+            b.step_captured(n)
+            assert np.array_equal(a.get(), b.get()), n
+            b.conservation()  # eager work between replays
