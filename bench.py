@@ -115,6 +115,34 @@ def probe_bandwidth(lbm, gib: float, reps: int = 10) -> dict:
     return out
 
 
+def small_lattice(lbm, inputs, reps: int = 5) -> dict:
+    """The 64 x 128 Rayleigh-Taylor workload (100 steps): launch-latency
+    bound (8,192 sites fill 128 wavefronts).  Median of `reps` runs of 100
+    steps for the fused and separate paths, plain launches and replayed
+    from a captured HIP graph."""
+    import statistics
+    import torch
+    ns = inputs.rt_config(64, 128)
+    rt = inputs.rt_perturbation(0, 128)
+    out = {}
+    for name, path in (("fused", lbm.LBM_PATH_FUSED), ("separate", lbm.LBM_PATH_SEPARATE)):
+        for mode in ("plain", "graph"):
+            lat = lbm.Lattice(lbm.config_from(ns, path=path)).init_rt(rt)
+            step = lat.step if mode == "plain" else lat.step_captured
+            step(100)
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                step(100)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            lat.close()
+            t = statistics.median(times)
+            out[f"{name}_{mode}"] = {"us_per_step": t / 100 * 1e6, "mlups": 64 * 128 * 100 / t / 1e6}
+    return out
+
+
 def kernel_bandwidth(kernels: dict, sites: int, lx: int, ly: int, elem_bytes: int = 8) -> dict:
     """Algorithmic GB/s per kernel: fused/propagate/collide read and write
     every population once (592 B per site in FP64, 296 B in FP32); bc reads
@@ -232,6 +260,10 @@ def main() -> int:
                "kernels": kernel_bandwidth(k4, sites, lx, ly)}
     log(f"regions: {regions['mlups']:.1f} MLUPS")
 
+    log("64x128 workload, 100 steps: plain and graph-captured launches")
+    small = small_lattice(lbm, inputs)
+    log("64x128: " + ", ".join(f"{k} {v['us_per_step']:.1f} us/step" for k, v in small.items()))
+
     fk = kern["fused"]
     traffic = measured_traffic(lx, ly)
     roofline = {"bound": "hbm", "achieved": fk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -255,6 +287,7 @@ def main() -> int:
                        "block": args.block or 256}},
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kern, "separate": separate,
         "bandwidth_probe": copy, "reduced_storage": reduced, "regions": regions,
+        "small_lattice_64x128": small,
         "paper_equivalent_gflops": 6472 * sites * args.steps / wall / 1e9,
     }
     print(json.dumps(out), flush=True)
