@@ -37,6 +37,7 @@ struct lbm_handle {
     hipGraphExec_t exec;
   };
   std::vector<Captured> captured;
+  hipStream_t cap = nullptr;  // private stream the step sequences are captured on
   // per-launch timing
   bool timing = false;
   std::vector<hipEvent_t> events;

@@ -340,16 +340,24 @@ int lbm_step_captured(lbm_handle* h, int32_t n) {
       LBM_HIP(h, hipEventCreateWithFlags(&h->ev_ready, hipEventDisableTiming));
       LBM_HIP(h, hipEventCreateWithFlags(&h->ev_halo, hipEventDisableTiming));
     }
-    LBM_HIP(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-    const int rc = lbm_step(h, n);
+    // capture on a private stream (the caller's may be the null stream,
+    // which cannot be captured); the graph is launched on the caller's
+    if (!h->cap) LBM_HIP(h, hipStreamCreate(&h->cap));
+    LBM_HIP(h, hipStreamSynchronize(h->stream));
+    hipStream_t user = h->stream;
+    h->stream = h->cap;
+    hipError_t eb = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
+    const int rc = eb == hipSuccess ? lbm_step(h, n) : LBM_EDEVICE;
     hipGraph_t graph = nullptr;
-    const hipError_t e = hipStreamEndCapture(h->stream, &graph);
+    const hipError_t e = eb == hipSuccess ? hipStreamEndCapture(h->cap, &graph) : eb;
+    h->stream = user;
     h->cur = start;  // the capture only recorded the steps
-    if (rc != LBM_OK) {
+    if (rc != LBM_OK || e != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
-      return rc;
+      (void)hipGetLastError();
+      if (rc != LBM_OK && eb == hipSuccess) return rc;
+      return fail(h, LBM_EDEVICE, std::string("stream capture: ") + hipGetErrorString(e));
     }
-    if (e != hipSuccess) return fail(h, LBM_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
     const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (ei != hipSuccess) {
       (void)hipGraphDestroy(graph);
@@ -593,6 +601,7 @@ void lbm_destroy(lbm_handle* h) {
       (void)hipGraphExecDestroy(c.exec);
       (void)hipGraphDestroy(c.graph);
     }
+    if (h->cap) (void)hipStreamDestroy(h->cap);
     if (h->side) {
       (void)hipStreamSynchronize(h->side);
       (void)hipStreamDestroy(h->side);
