@@ -32,7 +32,7 @@ struct lbm_handle {
   hipEvent_t ev_halo = nullptr;
   // captured step sequences: (n, starting buffer) -> instantiated graph
   struct Captured {
-    int n, cur;
+    int n, cur, cur_after;  // steps, buffer at start and at the end
     hipGraph_t graph;
     hipGraphExec_t exec;
   };

@@ -331,8 +331,12 @@ int lbm_step_captured(lbm_handle* h, int32_t n) {
   DeviceGuard dg(h->device);
   const int start = h->cur;
   hipGraphExec_t exec = nullptr;
+  int cur_after = start;
   for (const auto& c : h->captured)
-    if (c.n == n && c.cur == start) exec = c.exec;
+    if (c.n == n && c.cur == start) {
+      exec = c.exec;
+      cur_after = c.cur_after;
+    }
   if (!exec) {
     if (h->cfg.path == LBM_PATH_REGIONS && !h->side) {
       // create the side stream outside the capture
@@ -351,7 +355,8 @@ int lbm_step_captured(lbm_handle* h, int32_t n) {
     hipGraph_t graph = nullptr;
     const hipError_t e = eb == hipSuccess ? hipStreamEndCapture(h->cap, &graph) : eb;
     h->stream = user;
-    h->cur = start;  // the capture only recorded the steps
+    cur_after = h->cur;  // where the recorded steps leave the state
+    h->cur = start;      // the capture only recorded them
     if (rc != LBM_OK || e != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
       (void)hipGetLastError();
@@ -363,10 +368,10 @@ int lbm_step_captured(lbm_handle* h, int32_t n) {
       (void)hipGraphDestroy(graph);
       return fail(h, LBM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
     }
-    h->captured.push_back({n, start, graph, exec});
+    h->captured.push_back({n, start, cur_after, graph, exec});
   }
   LBM_HIP(h, hipGraphLaunch(exec, h->stream));
-  h->cur = start ^ (n & 1);
+  h->cur = cur_after;
   return LBM_OK;
 }
 
