@@ -69,7 +69,9 @@ struct CodecF16Dev {
   const double* inv_ref;
   __device__ double dec(S v, int l, int y) const {
     const double c = weight_of(l) * ref[y];
-    return c * (1.0 + static_cast<double>(static_cast<float>(v)));
+    // c (1 + d) rounded once: 1 + d is exact, so the fused multiply-add
+    // c d + c is the same correctly rounded value
+    return fma(c, static_cast<double>(static_cast<float>(v)), c);
   }
   __device__ S enc(double f, int l, int y) const {
     const double c = weight_of(l) * ref[y];
