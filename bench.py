@@ -29,7 +29,9 @@ METRIC = "D2Q37 MLUPS, FP64 vs FP32-storage, 1 GPU; ensemble p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_SITE_FP64 = 2 * 37 * 8  # one read + one write of every population
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fused_2048x8192.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1703_00185_amd", "csrc", "kernels.hip")
+# the sources the fused kernel is compiled from
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1703_00185_amd", "csrc", f) for f in
+                  ("kernels.hip", "d2q37_device.hpp", "kernels.hpp", "d2q37_model.hpp")]
 
 
 def log(msg: str) -> None:
@@ -37,19 +39,24 @@ def log(msg: str) -> None:
 
 
 def kernel_source_sha() -> str:
-    with open(KERNEL_SOURCE, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
-def measured_traffic(lx: int, ly: int):
+def measured_traffic(lx: int, ly: int, layout: str):
     """HBM bytes per fused launch from the committed rocprofv3 counter
-    summary, or None when it is missing or the kernel source changed."""
+    summary, or None when it is missing, was taken on another workload or
+    layout, or the kernel sources changed since."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha") != kernel_source_sha() or t.get("lx") != lx or t.get("ly") != ly:
+    if (t.get("kernel_source_sha") != kernel_source_sha() or t.get("lx") != lx or t.get("ly") != ly
+            or t.get("layout") != layout):
         return None
     return t.get("bytes_per_launch")
 
@@ -191,7 +198,9 @@ def main() -> int:
     ap.add_argument("--ly", type=int, default=8192)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--ny-pad", type=int, default=-1)
-    ap.add_argument("--plane-pad", type=int, default=-1)
+    ap.add_argument("--stride-pad", type=int, default=-1)
+    ap.add_argument("--layout", choices=["column", "planar"], default="column",
+                    help="population layout of the timed paths (planar is also timed for comparison)")
     ap.add_argument("--no-separate", action="store_true", help="time the fused path only")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -217,7 +226,9 @@ def main() -> int:
     sites = lx * ly
     ns = inputs.rt_config(lx, ly)
     rt = inputs.rt_perturbation(0, ly)
-    extra = {"block": args.block, "ny_pad": args.ny_pad, "plane_pad": args.plane_pad}
+    layout_kind = lbm.LBM_LAYOUT_PLANAR if args.layout == "planar" else lbm.LBM_LAYOUT_COLUMN
+    extra = {"block": args.block, "ny_pad": args.ny_pad, "stride_pad": args.stride_pad,
+             "layout": layout_kind}
 
     copy = probe_bandwidth(lbm, args.copy_gib) if args.copy_gib > 0 else None
     if copy:
@@ -232,6 +243,15 @@ def main() -> int:
     if cons[4] != 0:
         log(f"non-finite populations after the run: {cons[4]}")
         return 1
+
+    other = "planar" if args.layout == "column" else "column"
+    log(f"fused path, {other} layout {lx}x{ly}: {args.warmup} warmup + {args.steps} timed steps")
+    w5, k5, _, _ = time_path(lbm, ns, rt, lbm.LBM_PATH_FUSED, args.steps, args.warmup,
+                             dict(extra, layout=lbm.LBM_LAYOUT_COLUMN + lbm.LBM_LAYOUT_PLANAR - layout_kind))
+    other_layout = {"layout": other, "mlups": sites * args.steps / w5 / 1e6,
+                    "ms_per_step": w5 / args.steps * 1e3, "kernels": kernel_bandwidth(k5, sites, lx, ly)}
+    log(f"{other} layout: {other_layout['mlups']:.1f} MLUPS, "
+        f"fused kernel {other_layout['kernels']['fused']['gbs']:.0f} GB/s")
 
     separate = None
     if not args.no_separate:
@@ -265,7 +285,7 @@ def main() -> int:
     log("64x128: " + ", ".join(f"{k} {v['us_per_step']:.1f} us/step" for k, v in small.items()))
 
     fk = kern["fused"]
-    traffic = measured_traffic(lx, ly)
+    traffic = measured_traffic(lx, ly, args.layout)
     roofline = {"bound": "hbm", "achieved": fk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": fk["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": "fused_kernel (propagate+bc+collide)",
@@ -283,10 +303,11 @@ def main() -> int:
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"rayleigh_taylor_{lx}x{ly}_fp64", "lx": lx, "ly": ly,
                    "path": "fused", "storage": "fp64", "layout": {
-                       "nx": layout[0], "ny_pitch": layout[1], "plane_elems": layout[2],
-                       "block": args.block or 256}},
+                       "kind": args.layout, "nx": layout[0], "ny_pitch": layout[1],
+                       "pstride": layout[2], "cstride": layout[3], "block": args.block or 256}},
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kern, "separate": separate,
         "bandwidth_probe": copy, "reduced_storage": reduced, "regions": regions,
+        "other_layout": other_layout,
         "small_lattice_64x128": small,
         "paper_equivalent_gflops": 6472 * sites * args.steps / wall / 1e9,
     }

@@ -74,6 +74,23 @@ typedef enum {
                             LBM_PATH_FUSED bit for bit */
 } lbm_path;
 
+/* Population layout in each lattice copy.  Columns X = 0 .. Lx+5 include
+ * 3 halo columns per side (physical column x is X = x + 3); each
+ * population of a column is a run of NY contiguous rows (NY >= Ly, rows
+ * >= Ly unused), so the lanes of a wavefront, which take consecutive rows,
+ * touch one contiguous segment per population: the structure-of-arrays
+ * principle of Sec. 4 (Data Structure Analysis).  Element (l, X, y) sits at
+ * l * pstride + X * cstride + y (lbm_layout reports both strides). */
+typedef enum {
+  LBM_LAYOUT_COLUMN = 0, /* f[X][l][y]: the 37 runs of a column back to
+                            back (pstride = NY, cstride = 37 NY + pad);
+                            the default: a work-group's tile streams
+                            through one contiguous column block */
+  LBM_LAYOUT_PLANAR = 1  /* f[l][X][y]: one plane per population, as in
+                            Sec. 4 (cstride = NY, pstride = (Lx + 6) NY
+                            rounded up to 64, + pad) */
+} lbm_layout_kind;
+
 /* Single phases for lbm_run_phase and the timing counters. */
 typedef enum {
   LBM_PHASE_PBC = 0,       /* copy the periodic-x halo columns (in place) */
@@ -94,10 +111,13 @@ typedef struct {
   double t_top;      /* wall temperature of rows Ly-3..Ly-1 (> 0) */
   int32_t storage;   /* lbm_storage */
   int32_t path;      /* lbm_path used by lbm_step */
+  int32_t layout;    /* lbm_layout_kind */
   int32_t block;     /* work-group size of the lattice kernels: 64, 128,
                         256, 512 or 1024; 0 selects the default (256) */
-  int32_t ny_pad;    /* extra elements in the column pitch; < 0 default */
-  int64_t plane_pad; /* extra elements between population planes; < 0 default */
+  int32_t ny_pad;    /* extra elements in the row pitch NY; < 0 default */
+  int64_t stride_pad; /* extra elements on the outer stride (cstride for
+                         the column layout, pstride for the planar one);
+                         < 0 default */
 } lbm_config;
 
 /* Rayleigh-Taylor initial state (the initial assignment of Sec. 2; the
@@ -118,7 +138,8 @@ typedef struct {
 #define LBM_MAX_MODES 32
 
 /* Fill *cfg with defaults for an lx x ly lattice: tau 0.8, g = (0, -1e-4),
- * walls 1.05 (bottom) / 0.95 (top), FP64, fused path, default tiling. */
+ * walls 1.05 (bottom) / 0.95 (top), FP64, fused path, column layout,
+ * default tiling. */
 int lbm_config_default(lbm_config *cfg, int32_t lx, int32_t ly);
 
 /* Bytes of device memory needed for cfg (two lattice copies with halos,
@@ -180,7 +201,7 @@ int lbm_set_populations(lbm_handle *h, const double *host);
 
 /* Populations of n selected sites of the current state: out[l * n + i] =
  * f_l(xs[i], ys[i]), host arrays, 0 <= xs[i] < Lx, 0 <= ys[i] < Ly (checked
- * on the host: EINVAL otherwise).  n may be at most lbm_layout()[3] / 304.
+ * on the host: EINVAL otherwise).  n may be at most lbm_layout()[4] / 304.
  * Uses the idle lattice copy as scratch.  Synchronises the stream. */
 int lbm_get_sites(lbm_handle *h, int32_t n, const int32_t *xs, const int32_t *ys, double *out);
 
@@ -199,9 +220,10 @@ int lbm_set_timing(lbm_handle *h, int32_t enable);
 int lbm_read_timing(lbm_handle *h, double ms[LBM_NPHASES], int64_t count[LBM_NPHASES]);
 
 /* Geometry of the bound lattice: out[0] columns NX = Lx + 6 (3 halo
- * columns each side), out[1] column pitch NY (elements), out[2] population
- * plane stride (elements), out[3] bytes of one lattice copy. */
-int lbm_layout(const lbm_handle *h, int64_t out[4]);
+ * columns each side), out[1] row pitch NY (elements), out[2] pstride and
+ * out[3] cstride (elements; element (l, X, y) at l pstride + X cstride + y),
+ * out[4] bytes of one lattice copy. */
+int lbm_layout(const lbm_handle *h, int64_t out[5]);
 
 /* Model constants as the library uses them (host only, no GPU): hops
  * e[37][2], opposite index opp[37], weights w[37], velocity scale r.  Any

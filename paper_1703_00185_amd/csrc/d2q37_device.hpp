@@ -35,9 +35,10 @@ template <class S>
 __device__ __forceinline__ S ld(const S* base, unsigned byte_off) {
   return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + byte_off);
 }
+// Non-temporal store (streaming: no reuse expected from the caches).
 template <class S>
-__device__ __forceinline__ void st(S* base, unsigned byte_off, S v) {
-  *reinterpret_cast<S*>(reinterpret_cast<char*>(base) + byte_off) = v;
+__device__ __forceinline__ void st_nt(S* base, unsigned byte_off, S v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<S*>(reinterpret_cast<char*>(base) + byte_off));
 }
 
 // Population storage codecs.  Arithmetic is binary64 for every storage;

@@ -43,7 +43,7 @@ __device__ __forceinline__ void gather_wrap_interior(const SlotDesc& d, const C&
   for (int l = 0; l < NPOP; ++l) {
     const int col = wrap_col(x, EX[l], d.lx) + HALO;
     const GLOBAL_AS S* base =
-        src + (static_cast<long long>(l) * d.plane + static_cast<long long>(col) * d.ny - EY[l]);
+        src + (static_cast<long long>(l) * d.pstride + static_cast<long long>(col) * d.cstride - EY[l]);
     f[l] = cd.dec(base[uy], l, y - EY[l]);
   }
 }
@@ -58,8 +58,8 @@ __device__ __forceinline__ void gather_wrap_wall(const SlotDesc& d, const C& cd,
     const bool inside = (ys >= 0) && (ys < d.ly);
     const long long col = wrap_col(x, EX[l], d.lx) + HALO;
     const long long idx = inside
-        ? static_cast<long long>(l) * d.plane + col * d.ny + ys
-        : static_cast<long long>(opp_of(l)) * d.plane + static_cast<long long>(x + HALO) * d.ny + y;
+        ? static_cast<long long>(l) * d.pstride + col * d.cstride + ys
+        : static_cast<long long>(opp_of(l)) * d.pstride + static_cast<long long>(x + HALO) * d.cstride + y;
     f[l] = cd.dec(src[idx], l, inside ? ys : y);
   }
 }
@@ -86,9 +86,11 @@ __device__ __forceinline__ void step_tile(const SlotDesc& d, int x, int yb) {
   collide_site(f, d.cp);
   if (y < d.ly) {
     const unsigned site = static_cast<unsigned>(y);
-    GLOBAL_AS S* col = dst + static_cast<long long>(x + HALO) * d.ny;
+    GLOBAL_AS S* col = dst + static_cast<long long>(x + HALO) * d.cstride;
+    // non-temporal: every element is written once per step
 #pragma unroll
-    for (int l = 0; l < NPOP; ++l) (col + static_cast<long long>(l) * d.plane)[site] = cd.enc(f[l], l, y);
+    for (int l = 0; l < NPOP; ++l)
+      __builtin_nontemporal_store(cd.enc(f[l], l, y), &(col + static_cast<long long>(l) * d.pstride)[site]);
   }
 }
 

@@ -9,13 +9,15 @@
 namespace d2q37 {
 
 // One lattice of the ensemble, as the step kernel reads it.  The lattice
-// keeps the single-lattice layout (37 planes, 3 unused halo columns per
-// side); the engine wraps x instead of refreshing halos.
+// keeps its single-lattice layout (element (l, X, y) at l pstride +
+// X cstride + y, 3 unused halo columns per side); the engine wraps x
+// instead of refreshing halos.
 struct SlotDesc {
   char* buf[2];
-  long long plane;  // population plane stride, elements
+  long long pstride;  // elements between populations of a site
+  long long cstride;  // elements between columns
   int storage;      // STORAGE_F64 or STORAGE_F32
-  int lx, ly, ny;   // lattice size, column pitch
+  int lx, ly;       // lattice size
   int ny_blocks;    // ceil(ly / engine block)
   int cur;          // buffer holding the current populations
   int steps_left;   // steps still to run; 0 = finished (not stepped)

@@ -304,11 +304,11 @@ int lbm_engine_add(lbm_engine* e, lbm_handle* h, int32_t steps, int32_t* slot) {
   SlotDesc d{};
   d.buf[0] = h->buf[0];
   d.buf[1] = h->buf[1];
-  d.plane = h->geo.plane;
+  d.pstride = h->geo.pstride;
+  d.cstride = h->geo.cstride;
   d.storage = h->geo.storage;
   d.lx = h->geo.lx;
   d.ly = h->geo.ly;
-  d.ny = h->geo.ny;
   d.ny_blocks = (d.ly + e->block - 1) / e->block;
   d.cur = h->cur;
   d.steps_left = steps;

@@ -1,9 +1,10 @@
 // gfx950 kernels of the D2Q37 thermal lattice Boltzmann step.
 //
 // One lane per lattice site, lanes of a wavefront along y (the contiguous
-// direction of each population plane), so that each of the 37 population
-// loads and stores of a wavefront is one contiguous 512-byte segment
-// (structure-of-arrays layout, Sec. 4 "Data Structure Analysis").
+// direction of each population run), so that each of the 37 population
+// loads and stores of a wavefront is one contiguous segment of 64 elements
+// (the structure-of-arrays principle of Sec. 4 "Data Structure Analysis";
+// the column and planar layouts differ only in the two strides).
 //
 // Floating point: the file is compiled without contraction; every fused
 // multiply-add below is an explicit fma().  A kernel therefore rounds
@@ -45,19 +46,27 @@ __device__ __forceinline__ bool interior_wave(const Geometry& g, int ywave) {
   return __builtin_amdgcn_readfirstlane(ok) != 0;
 }
 
+// Start of the run of population l in column X, elements.
+__device__ __forceinline__ long long run_of(const Geometry& g, int l, int X) {
+  return static_cast<long long>(l) * g.pstride + static_cast<long long>(X) * g.cstride;
+}
+
 // Pull gather of Eq. (10): f_l(x, y) <- f_l(x - e_lx, y - e_ly).  Columns
 // x - e_lx < 0 or >= Lx read the halo columns filled by pbc.  Interior
-// form: the per-population offset is uniform and the per-lane byte offset
-// is shared by all 37 loads.
+// form, for a column x uniform over the work-group: the 37 source runs
+// start at uniform (scalar) addresses and all loads share the lane's byte
+// offset.
 template <class C>
 __device__ __forceinline__ void gather_interior(const Geometry& g, const C& cd,
                                                 const typename C::S* __restrict__ src, int x, int y,
                                                 double (&f)[NPOP]) {
   using S = typename C::S;
-  const unsigned off = static_cast<unsigned>((x + HALO) * g.ny + y) * static_cast<unsigned>(sizeof(S));
+  const unsigned off = static_cast<unsigned>(y) * static_cast<unsigned>(sizeof(S));
+  const S* col = src + static_cast<long long>(x + HALO) * g.cstride;
 #pragma unroll
   for (int l = 0; l < NPOP; ++l) {
-    const S* base = src + (static_cast<long long>(l) * g.plane - (EX[l] * g.ny + EY[l]));
+    const S* base = col + (static_cast<long long>(l) * g.pstride -
+                           (static_cast<long long>(EX[l]) * g.cstride + EY[l]));
     f[l] = cd.dec(ld(base, off), l, y - EY[l]);
   }
 }
@@ -73,30 +82,51 @@ __device__ __forceinline__ void gather_wall(const Geometry& g, const C& cd,
   for (int l = 0; l < NPOP; ++l) {
     const int ys = y - EY[l];
     const bool inside = (ys >= 0) && (ys < g.ly);
-    const long long idx = inside
-        ? static_cast<long long>(l) * g.plane + static_cast<long long>(X - EX[l]) * g.ny + ys
-        : static_cast<long long>(opp_of(l)) * g.plane + static_cast<long long>(X) * g.ny + y;
+    const long long idx = inside ? run_of(g, l, X - EX[l]) + ys : run_of(g, opp_of(l), X) + y;
     f[l] = cd.dec(src[idx], l, inside ? ys : y);  // opp(l) shares w_l
   }
 }
 
+// The 37 populations of site (x, y), x uniform over the work-group.
+template <class C>
+__device__ __forceinline__ void load_column_site(const Geometry& g, const C& cd,
+                                                 const typename C::S* __restrict__ src, int x, int y,
+                                                 double (&f)[NPOP]) {
+  using S = typename C::S;
+  const unsigned off = static_cast<unsigned>(y) * static_cast<unsigned>(sizeof(S));
+  const S* col = src + static_cast<long long>(x + HALO) * g.cstride;
+#pragma unroll
+  for (int l = 0; l < NPOP; ++l) f[l] = cd.dec(ld(col + static_cast<long long>(l) * g.pstride, off), l, y);
+}
+
+// Store of site (x, y), x uniform over the work-group.  Non-temporal: the
+// step kernels write every element once and nothing reads it back before
+// the next launch.
+template <class C>
+__device__ __forceinline__ void store_column_site(const Geometry& g, const C& cd,
+                                                  typename C::S* __restrict__ dst, int x, int y,
+                                                  const double (&f)[NPOP]) {
+  using S = typename C::S;
+  const unsigned off = static_cast<unsigned>(y) * static_cast<unsigned>(sizeof(S));
+  S* col = dst + static_cast<long long>(x + HALO) * g.cstride;
+#pragma unroll
+  for (int l = 0; l < NPOP; ++l) st_nt(col + static_cast<long long>(l) * g.pstride, off, cd.enc(f[l], l, y));
+}
+
+// Any site (x per lane).
 template <class C>
 __device__ __forceinline__ void load_site(const Geometry& g, const C& cd,
                                           const typename C::S* __restrict__ src, int x, int y,
                                           double (&f)[NPOP]) {
-  using S = typename C::S;
-  const unsigned off = static_cast<unsigned>((x + HALO) * g.ny + y) * static_cast<unsigned>(sizeof(S));
 #pragma unroll
-  for (int l = 0; l < NPOP; ++l) f[l] = cd.dec(ld(src + static_cast<long long>(l) * g.plane, off), l, y);
+  for (int l = 0; l < NPOP; ++l) f[l] = cd.dec(src[run_of(g, l, x + HALO) + y], l, y);
 }
 
 template <class C>
 __device__ __forceinline__ void store_site(const Geometry& g, const C& cd, typename C::S* __restrict__ dst,
                                            int x, int y, const double (&f)[NPOP]) {
-  using S = typename C::S;
-  const unsigned off = static_cast<unsigned>((x + HALO) * g.ny + y) * static_cast<unsigned>(sizeof(S));
 #pragma unroll
-  for (int l = 0; l < NPOP; ++l) st(dst + static_cast<long long>(l) * g.plane, off, cd.enc(f[l], l, y));
+  for (int l = 0; l < NPOP; ++l) dst[run_of(g, l, x + HALO) + y] = cd.enc(f[l], l, y);
 }
 
 // ---------------------------------------------------------------------------
@@ -144,8 +174,8 @@ __global__ void __launch_bounds__(256) pbc_kernel(S* __restrict__ f, Geometry g)
   const int d = kHalo.d[c];
   const int dst_col = kHalo.right[c] ? g.lx + HALO - 1 + d : HALO - d;
   const int src_col = kHalo.right[c] ? HALO - 1 + d : g.lx + HALO - d;
-  S* plane = f + static_cast<long long>(l) * g.plane;
-  plane[static_cast<long long>(dst_col) * g.ny + y] = plane[static_cast<long long>(src_col) * g.ny + y];
+  S* fl = f + static_cast<long long>(l) * g.pstride;
+  fl[static_cast<long long>(dst_col) * g.cstride + y] = fl[static_cast<long long>(src_col) * g.cstride + y];
 }
 
 // propagate (Sec. 4): pull gather into the other lattice copy.
@@ -161,7 +191,7 @@ __global__ void __launch_bounds__(BLOCK) propagate_kernel(const typename C::S* _
   } else {
     gather_wall(g, cd, src, x, y < g.ly ? y : g.ly - 1, f);
   }
-  if (y < g.ly) store_site(g, cd, dst, x, y, f);
+  if (y < g.ly) store_column_site(g, cd, dst, x, y, f);
 }
 
 // bc (Sec. 4): thermal walls, in place, on the 3 bottom and 3 top rows.
@@ -190,9 +220,9 @@ __global__ void __launch_bounds__(BLOCK) collide_kernel(const typename C::S* __r
   lane_site<BLOCK>(g, ColumnSet{0, g.lx, 0}, x, y, ywave);
   if (y >= g.ly) return;
   double f[NPOP];
-  load_site(g, cd, src, x, y, f);
+  load_column_site(g, cd, src, x, y, f);
   collide_site(f, c);
-  store_site(g, cd, dst, x, y, f);
+  store_column_site(g, cd, dst, x, y, f);
 }
 
 // propagate + bc + collide in registers: one read and one write of every
@@ -214,7 +244,7 @@ __global__ void __launch_bounds__(BLOCK) fused_kernel(const typename C::S* __res
     if (yc < WALL_ROWS || yc >= g.ly - WALL_ROWS) thermalise(f, yc < WALL_ROWS, w);
   }
   collide_site(f, c);
-  if (y < g.ly) store_site(g, cd, dst, x, y, f);
+  if (y < g.ly) store_column_site(g, cd, dst, x, y, f);
 }
 
 // Per-site rho, ux, uy, T into out[4][lx][ly] (Sec. 2 moment definitions;
@@ -342,7 +372,6 @@ __device__ __forceinline__ void rt_fields(const RtParams& p, int y, double h, do
 template <class C>
 __global__ void __launch_bounds__(256) init_rt_kernel(typename C::S* __restrict__ f, Geometry g,
                                                       RtParams p) {
-  using S = typename C::S;
   const C cd{g.ref, g.inv_ref};
   const long long n = static_cast<long long>(g.lx) * g.ly;
   const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
@@ -357,12 +386,11 @@ __global__ void __launch_bounds__(256) init_rt_kernel(typename C::S* __restrict_
   double rho, temp;
   rt_fields(p, y, h, rho, temp);
   const double th = temp - 1.0;
-  const unsigned off = static_cast<unsigned>((x + HALO) * g.ny + y) * static_cast<unsigned>(sizeof(S));
 #pragma unroll
   for (int l = 0; l < NPOP; ++l) {
     const double C2 = R2 * static_cast<double>(EX[l] * EX[l] + EY[l] * EY[l]);
     const double k = weight_of(l) * ((1.0 + th * (C2 - 2.0) / 2.0) + th * th * (C2 * C2 - 8.0 * C2 + 8.0) / 8.0);
-    st(f + static_cast<long long>(l) * g.plane, off, cd.enc(rho * k, l, y));
+    f[run_of(g, l, x + HALO) + y] = cd.enc(rho * k, l, y);
   }
 }
 
@@ -379,11 +407,11 @@ __global__ void __launch_bounds__(256) rt_reference_kernel(double* __restrict__ 
   inv_ref[y] = 1.0 / rho;
 }
 
-// Host-array transfers through the codec: one population plane at a time
-// between binary64 values [x][y] and the stored plane.
+// Host-array transfers through the codec: one population at a time
+// between binary64 values [x][y] and its stored runs.
 template <class C>
 __global__ void __launch_bounds__(256) encode_plane_kernel(const double* __restrict__ in,
-                                                           typename C::S* __restrict__ plane,
+                                                           typename C::S* __restrict__ f,
                                                            Geometry g, int l) {
   const C cd{g.ref, g.inv_ref};
   const long long n = static_cast<long long>(g.lx) * g.ly;
@@ -391,11 +419,11 @@ __global__ void __launch_bounds__(256) encode_plane_kernel(const double* __restr
   if (i >= n) return;
   const int x = static_cast<int>(i / g.ly);
   const int y = static_cast<int>(i - static_cast<long long>(x) * g.ly);
-  plane[static_cast<long long>(x + HALO) * g.ny + y] = cd.enc(in[i], l, y);
+  f[run_of(g, l, x + HALO) + y] = cd.enc(in[i], l, y);
 }
 
 template <class C>
-__global__ void __launch_bounds__(256) decode_plane_kernel(const typename C::S* __restrict__ plane,
+__global__ void __launch_bounds__(256) decode_plane_kernel(const typename C::S* __restrict__ f,
                                                            double* __restrict__ out, Geometry g, int l) {
   const C cd{g.ref, g.inv_ref};
   const long long n = static_cast<long long>(g.lx) * g.ly;
@@ -403,7 +431,7 @@ __global__ void __launch_bounds__(256) decode_plane_kernel(const typename C::S* 
   if (i >= n) return;
   const int x = static_cast<int>(i / g.ly);
   const int y = static_cast<int>(i - static_cast<long long>(x) * g.ly);
-  out[i] = cd.dec(plane[static_cast<long long>(x + HALO) * g.ny + y], l, y);
+  out[i] = cd.dec(f[run_of(g, l, x + HALO) + y], l, y);
 }
 
 // ---------------------------------------------------------------------------
@@ -558,7 +586,7 @@ hipError_t launch_encode_plane(const Geometry& g, const double* in, void* f, int
   const long long n = static_cast<long long>(g.lx) * g.ly;
   (void)hipGetLastError();
   D2Q37_STORAGE(g, hipLaunchKernelGGL(encode_plane_kernel<C>, dim3(static_cast<unsigned>((n + 255) / 256)),
-                                      dim3(256), 0, s, in, static_cast<S*>(f) + l * g.plane, g, l));
+                                      dim3(256), 0, s, in, static_cast<S*>(f), g, l));
   return hipGetLastError();
 }
 
@@ -566,7 +594,7 @@ hipError_t launch_decode_plane(const Geometry& g, const void* f, double* out, in
   const long long n = static_cast<long long>(g.lx) * g.ly;
   (void)hipGetLastError();
   D2Q37_STORAGE(g, hipLaunchKernelGGL(decode_plane_kernel<C>, dim3(static_cast<unsigned>((n + 255) / 256)),
-                                      dim3(256), 0, s, static_cast<const S*>(f) + l * g.plane, out, g, l));
+                                      dim3(256), 0, s, static_cast<const S*>(f), out, g, l));
   return hipGetLastError();
 }
 

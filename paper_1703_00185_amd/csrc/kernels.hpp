@@ -7,21 +7,31 @@
 
 namespace d2q37 {
 
-// Lattice geometry in HBM.  Populations are structure-of-arrays planes
-// f[l][X][y]: X in [0, lx + 6) counts columns including 3 halo columns on
-// each side (physical column x is X = x + 3), y in [0, ny) is the row, with
-// rows >= ly being padding that is never read.  Element (l, X, y) sits at
-// l * plane + X * ny + y.
 // Population storage types.
 enum Storage : int { STORAGE_F64 = 0, STORAGE_F32 = 1, STORAGE_F16DEV = 2 };
 
+// Population layouts.  X in [0, lx + 6) counts columns including 3 halo
+// columns on each side (physical column x is X = x + 3), y in [0, ny) is
+// the row, with rows >= ly being padding that is never read.  Element
+// (l, X, y) sits at l * pstride + X * cstride + y:
+//  * COLUMN f[X][l][y]: pstride = ny, cstride = 37 ny (+ pad).  Each column
+//    holds its 37 population runs back to back, so a work-group's tile
+//    streams through one contiguous column block;
+//  * PLANAR f[l][X][y]: cstride = ny, pstride = (lx + 6) ny (+ pad), the
+//    structure-of-arrays planes of Sec. 4 "Data Structure Analysis".
+// In both, each population of a column is ny contiguous rows, so the 64
+// lanes of a wavefront (consecutive rows) touch one contiguous segment.
+enum PopLayout : int { LAYOUT_COLUMN = 0, LAYOUT_PLANAR = 1 };
+
 struct Geometry {
   int lx, ly;
-  int storage;       // Storage: element type of the population planes
-  int ny;            // column pitch, elements
+  int storage;       // Storage: element type of the populations
+  int layout;        // PopLayout
+  int ny;            // rows per column run (pitch), elements
   int block;         // work-group size of the lattice kernels
   int ny_blocks;     // ceil(ly / block)
-  long long plane;   // population plane stride, elements
+  long long pstride; // elements between populations l and l + 1 of a site
+  long long cstride; // elements between columns X and X + 1
   const double* ref;      // per-row reference density (deviation storage)
   const double* inv_ref;  // its reciprocal
 };

@@ -19,7 +19,7 @@ using namespace d2q37::host;
 
 namespace {
 
-constexpr long long kMaxPlaneElems = (1LL << 29);  // byte offsets inside a plane fit 32 bits
+constexpr long long kMaxSites = (1LL << 29);  // (lx + 6) * pitch; row byte offsets fit 32 bits
 
 long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
 
@@ -42,42 +42,49 @@ int make_layout(const lbm_config* c, Layout* out, std::string* why) {
     return *why = "wall temperatures must be finite and > 0", LBM_EINVAL;
   if (c->storage != LBM_FP64 && c->storage != LBM_FP32 && c->storage != LBM_FP16DEV)
     return *why = "storage must be LBM_FP64, LBM_FP32 or LBM_FP16DEV", LBM_EINVAL;
+  if (c->layout != LBM_LAYOUT_COLUMN && c->layout != LBM_LAYOUT_PLANAR)
+    return *why = "layout must be LBM_LAYOUT_COLUMN or LBM_LAYOUT_PLANAR", LBM_EINVAL;
   if (c->path != LBM_PATH_SEPARATE && c->path != LBM_PATH_FUSED && c->path != LBM_PATH_REGIONS)
     return *why = "path must be LBM_PATH_SEPARATE, LBM_PATH_FUSED or LBM_PATH_REGIONS", LBM_EINVAL;
   const int block = c->block == 0 ? 256 : c->block;
   if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
     return *why = "block must be 0, 64, 128, 256, 512 or 1024", LBM_EINVAL;
   if (c->ny_pad > (1 << 20)) return *why = "ny_pad too large", LBM_EINVAL;
-  if (c->plane_pad > (1LL << 24)) return *why = "plane_pad too large", LBM_EINVAL;
+  if (c->stride_pad > (1LL << 24)) return *why = "stride_pad too large", LBM_EINVAL;
 
   Geometry g{};
   g.lx = c->lx;
   g.ly = c->ly;
   g.storage = c->storage == LBM_FP32 ? STORAGE_F32
               : c->storage == LBM_FP16DEV ? STORAGE_F16DEV : STORAGE_F64;
+  g.layout = c->layout == LBM_LAYOUT_PLANAR ? LAYOUT_PLANAR : LAYOUT_COLUMN;
   g.block = block;
   const long long ny = round_up(c->ly, 64) + (c->ny_pad > 0 ? c->ny_pad : 0);
   const long long nx = static_cast<long long>(c->lx) + 2 * HALO;
-  if (nx * ny >= kMaxPlaneElems)
+  if (nx * ny >= kMaxSites)
     return *why = "lattice too large: (lx + 6) * pitch must stay below 2^29 sites", LBM_EINVAL;
   g.ny = static_cast<int>(ny);
   g.ny_blocks = (c->ly + block - 1) / block;
   if (static_cast<long long>(c->lx) * g.ny_blocks >= (1LL << 31))
     return *why = "too many work-groups", LBM_EINVAL;
-  g.plane = round_up(nx * ny, 64) + (c->plane_pad > 0 ? c->plane_pad : 0);
+  const long long pad = c->stride_pad > 0 ? c->stride_pad : 0;
+  long long elems;
+  if (g.layout == LAYOUT_PLANAR) {
+    g.cstride = ny;
+    g.pstride = round_up(nx * ny, 64) + pad;
+    elems = NPOP * g.pstride;
+  } else {
+    g.pstride = ny;
+    g.cstride = NPOP * ny + pad;
+    elems = nx * g.cstride;
+  }
   out->geo = g;
-  out->buf_bytes =
-      static_cast<size_t>(round_up(static_cast<long long>(NPOP) * g.plane * elem_bytes(g), 256));
+  out->buf_bytes = static_cast<size_t>(round_up(elems * elem_bytes(g), 256));
   out->ref_bytes = g.storage == STORAGE_F16DEV ? static_cast<size_t>(round_up(8LL * c->ly, 256)) : 0;
   // host transfers stage one plane of binary64 values in the idle copy
   if (static_cast<size_t>(8) * c->lx * c->ly > out->buf_bytes)
     return *why = "internal: staging does not fit", LBM_EINVAL;
   return LBM_OK;
-}
-
-// Byte offset of physical column 0 of population l.
-size_t plane_col0(const Geometry& g, int l) {
-  return (static_cast<size_t>(l) * g.plane + static_cast<size_t>(HALO) * g.ny) * elem_bytes(g);
 }
 
 // Launch with optional timing events around it.
@@ -189,9 +196,10 @@ int lbm_config_default(lbm_config* cfg, int32_t lx, int32_t ly) {
   cfg->t_top = 0.95;
   cfg->storage = LBM_FP64;
   cfg->path = LBM_PATH_FUSED;
+  cfg->layout = LBM_LAYOUT_COLUMN;
   cfg->block = 0;
   cfg->ny_pad = -1;
-  cfg->plane_pad = -1;
+  cfg->stride_pad = -1;
   return LBM_OK;
 }
 
@@ -551,12 +559,13 @@ int lbm_read_timing(lbm_handle* h, double ms[LBM_NPHASES], int64_t count[LBM_NPH
   return LBM_OK;
 }
 
-int lbm_layout(const lbm_handle* h, int64_t out[4]) {
+int lbm_layout(const lbm_handle* h, int64_t out[5]) {
   if (!h || !out) return fail(nullptr, LBM_EINVAL, "handle/out is NULL");
   out[0] = h->geo.lx + 2 * HALO;
   out[1] = h->geo.ny;
-  out[2] = h->geo.plane;
-  out[3] = static_cast<int64_t>(h->buf_bytes);
+  out[2] = h->geo.pstride;
+  out[3] = h->geo.cstride;
+  out[4] = static_cast<int64_t>(h->buf_bytes);
   return LBM_OK;
 }
 

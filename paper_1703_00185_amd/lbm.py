@@ -24,6 +24,7 @@ MAX_MODES = 32
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ESTATE = 0, -1, -2, -3, -4
 LBM_FP64, LBM_FP32, LBM_FP16DEV = 0, 1, 2
 LBM_PATH_SEPARATE, LBM_PATH_FUSED, LBM_PATH_REGIONS = 0, 1, 2
+LBM_LAYOUT_COLUMN, LBM_LAYOUT_PLANAR = 0, 1
 (LBM_PHASE_PBC, LBM_PHASE_PROPAGATE, LBM_PHASE_BC, LBM_PHASE_COLLIDE,
  LBM_PHASE_FUSED, LBM_PHASE_FUSED_BULK, LBM_PHASE_FUSED_BORDER) = range(7)
 LBM_NPHASES = 7
@@ -40,8 +41,8 @@ class LbmError(RuntimeError):
 class lbm_config(ctypes.Structure):
     _fields_ = [("lx", c_int32), ("ly", c_int32), ("tau", c_double), ("gx", c_double),
                 ("gy", c_double), ("t_bottom", c_double), ("t_top", c_double),
-                ("storage", c_int32), ("path", c_int32), ("block", c_int32),
-                ("ny_pad", c_int32), ("plane_pad", c_int64)]
+                ("storage", c_int32), ("path", c_int32), ("layout", c_int32), ("block", c_int32),
+                ("ny_pad", c_int32), ("stride_pad", c_int64)]
 
 
 class lbm_rt_params(ctypes.Structure):
@@ -227,7 +228,8 @@ def lbm_read_timing(h):
 
 
 def lbm_layout(h):
-    out = np.zeros(4, dtype=np.int64)
+    """(NX, NY, pstride, cstride, bytes of one lattice copy)."""
+    out = np.zeros(5, dtype=np.int64)
     _check(load().lbm_layout(h, _ptr(out)), h)
     return tuple(int(v) for v in out)
 
@@ -449,6 +451,9 @@ def config_from(ns, **overrides) -> lbm_config:
     cfg = lbm_config_default(ns.lx, ns.ly)
     cfg.tau, cfg.gx, cfg.gy = ns.tau, ns.gx, ns.gy
     cfg.t_bottom, cfg.t_top = ns.t_bottom, ns.t_top
+    fields = {name for name, _ in lbm_config._fields_}
     for k, v in overrides.items():
+        if k not in fields:
+            raise TypeError(f"lbm_config has no field {k!r}")
         setattr(cfg, k, v)
     return cfg

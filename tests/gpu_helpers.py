@@ -12,6 +12,7 @@ import oracle
 from paper_1703_00185_amd import inputs, lbm
 
 FP64_TOL = 1e-12
+LAYOUTS = [lbm.LBM_LAYOUT_COLUMN, lbm.LBM_LAYOUT_PLANAR]
 
 
 def need_gpu():
@@ -34,7 +35,8 @@ def err_metric(got: np.ndarray, ref: np.ndarray) -> float:
 
 def lattice(ns, path=lbm.LBM_PATH_FUSED, block=0, **kw) -> lbm.Lattice:
     cfg = lbm.config_from(ns, path=path, block=block, **kw)
-    note(f"lattice {ns.lx}x{ns.ly} path={path} block={block}")
+    note(f"lattice {ns.lx}x{ns.ly} path={path} block={block} layout={cfg.layout} "
+         f"storage={cfg.storage}")
     return lbm.Lattice(cfg)
 
 

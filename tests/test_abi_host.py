@@ -50,17 +50,27 @@ def test_wall_factors_bit_equal(t):
 
 def test_required_bytes_layout():
     cfg = lbm.lbm_config_default(64, 128)
-    n = lbm.lbm_required_bytes(cfg)
+    assert cfg.layout == lbm.LBM_LAYOUT_COLUMN
     nx, ny = 64 + 6, 128
-    plane = -(-nx * ny // 64) * 64
-    assert n == 2 * (-(-37 * plane * 8 // 256) * 256)
+    for layout, pad, elems in ((lbm.LBM_LAYOUT_COLUMN, -1, nx * 37 * ny),
+                               (lbm.LBM_LAYOUT_PLANAR, -1, 37 * (-(-nx * ny // 64) * 64)),
+                               (lbm.LBM_LAYOUT_COLUMN, 10, nx * (37 * ny + 10)),
+                               (lbm.LBM_LAYOUT_PLANAR, 10, 37 * (-(-nx * ny // 64) * 64 + 10))):
+        cfg.layout, cfg.stride_pad = layout, pad
+        assert lbm.lbm_required_bytes(cfg) == 2 * (-(-elems * 8 // 256) * 256)
+
+
+def test_config_from_rejects_unknown_fields():
+    from paper_1703_00185_amd import inputs
+    with pytest.raises(TypeError):
+        lbm.config_from(inputs.rt_config(64, 128), plane_pad=3)
 
 
 @pytest.mark.parametrize("field,value,needle", [
     ("lx", 2, "lx"), ("ly", 5, "ly"), ("tau", 0.5, "tau"), ("tau", float("nan"), "tau"),
     ("t_bottom", 0.0, "temperature"), ("t_top", -1.0, "temperature"),
     ("gy", float("inf"), "gravity"), ("storage", 7, "storage"), ("path", 3, "path"),
-    ("block", 96, "block"),
+    ("block", 96, "block"), ("layout", 2, "layout"), ("layout", -1, "layout"),
 ])
 def test_invalid_config_rejected(field, value, needle):
     cfg = lbm.lbm_config_default(64, 128)

@@ -3,7 +3,7 @@
 Each lattice in the mix must end bit-identical to the same lattice stepped
 alone with lbm_step (the engine runs the fused kernel's arithmetic; only
 the tile order and the periodic wrap differ), whatever the tiling, the
-schedule, the storage mix and the order in which lattices join and leave.
+schedule, the storage and layout mix and the order in which lattices join and leave.
 One FP64 member is also checked against the oracle.
 """
 import numpy as np
@@ -15,15 +15,16 @@ from paper_1703_00185_amd import inputs, lbm
 
 pytestmark = pytest.mark.gpu
 
-# (lx, ly, storage, steps, tau, gravity, t_bottom, t_top)
+COL, PLA = lbm.LBM_LAYOUT_COLUMN, lbm.LBM_LAYOUT_PLANAR
+# (lx, ly, storage, steps, tau, gravity, t_bottom, t_top, layout)
 MIX = [
-    (64, 128, lbm.LBM_FP64, 9, 0.8, 1e-4, 1.05, 0.95),
-    (37, 70, lbm.LBM_FP32, 5, 0.7, 3e-4, 1.1, 0.9),
-    (130, 257, lbm.LBM_FP64, 12, 1.2, 1e-4, 1.02, 0.98),
-    (3, 6, lbm.LBM_FP64, 4, 0.8, 0.0, 1.0, 1.0),
-    (9, 1100, lbm.LBM_FP32, 7, 0.9, 2e-4, 1.08, 0.93),
-    (16, 32, lbm.LBM_FP64, 0, 0.8, 1e-4, 1.05, 0.95),
-    (256, 64, lbm.LBM_FP32, 3, 0.65, 1e-4, 1.15, 0.85),
+    (64, 128, lbm.LBM_FP64, 9, 0.8, 1e-4, 1.05, 0.95, COL),
+    (37, 70, lbm.LBM_FP32, 5, 0.7, 3e-4, 1.1, 0.9, PLA),
+    (130, 257, lbm.LBM_FP64, 12, 1.2, 1e-4, 1.02, 0.98, PLA),
+    (3, 6, lbm.LBM_FP64, 4, 0.8, 0.0, 1.0, 1.0, COL),
+    (9, 1100, lbm.LBM_FP32, 7, 0.9, 2e-4, 1.08, 0.93, COL),
+    (16, 32, lbm.LBM_FP64, 0, 0.8, 1e-4, 1.05, 0.95, PLA),
+    (256, 64, lbm.LBM_FP32, 3, 0.65, 1e-4, 1.15, 0.85, COL),
 ]
 
 
@@ -33,9 +34,9 @@ def _gpu():
 
 
 def _lattice(spec, seed):
-    lx, ly, storage, _, tau, grav, tb, tt = spec
+    lx, ly, storage, _, tau, grav, tb, tt, layout = spec
     ns = inputs.rt_config(lx, ly, tau=tau, gravity=grav, t_bottom=tb, t_top=tt)
-    cfg = lbm.config_from(ns, storage=storage)
+    cfg = lbm.config_from(ns, storage=storage, layout=layout)
     lat = lbm.Lattice(cfg)
     lat.init_rt(inputs.rt_perturbation(seed, ly))
     return lat, ns
@@ -77,7 +78,7 @@ def test_mix_equals_each_lattice_alone(tiling):
 def test_engine_member_matches_oracle():
     spec = MIX[0]
     got = _run_engine([spec, MIX[1], MIX[2]])[0]
-    lx, ly, _, steps, tau, grav, tb, tt = spec
+    lx, ly, _, steps, tau, grav, tb, tt, _ = spec
     ns = inputs.rt_config(lx, ly, tau=tau, gravity=grav, t_bottom=tb, t_top=tt)
     f = oracle.run(oracle.init_rt(lx, ly, ns, inputs.rt_perturbation(0, ly)), ns, steps)
     assert err_metric(got, f) < FP64_TOL

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_helpers import err_metric, lattice, need_gpu, noisy_state, note
+from gpu_helpers import LAYOUTS, err_metric, lattice, need_gpu, noisy_state, note
 from paper_1703_00185_amd import inputs, lbm
 
 pytestmark = pytest.mark.gpu
@@ -30,8 +30,8 @@ def _ref(ns, ly):
     return rho[0].copy()
 
 
-def _make(ns, path=lbm.LBM_PATH_FUSED):
-    lat = lattice(ns, path=path, storage=lbm.LBM_FP16DEV)
+def _make(ns, path=lbm.LBM_PATH_FUSED, layout=lbm.LBM_LAYOUT_COLUMN):
+    lat = lattice(ns, path=path, storage=lbm.LBM_FP16DEV, layout=layout)
     ref = _ref(ns, ns.ly)
     lbm.lbm_set_reference(lat.h, ref)
     return lat, ref
@@ -59,11 +59,12 @@ def test_fp16dev_roundtrip_propagate_bc(lx, ly):
     assert np.array_equal(b, oracle.stored(oracle.bc(want_p, ns.t_bottom, ns.t_top), "fp16dev", ref))
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("path", [lbm.LBM_PATH_SEPARATE, lbm.LBM_PATH_FUSED])
 @pytest.mark.parametrize("lx,ly", SIZES)
-def test_fp16dev_step_within_one_ulp(lx, ly, path):
+def test_fp16dev_step_within_one_ulp(lx, ly, path, layout):
     ns = inputs.rt_config(lx, ly)
-    lat, ref = _make(ns, path)
+    lat, ref = _make(ns, path, layout)
     with lat:
         f = oracle.stored(noisy_state(3, lx, ly), "fp16dev", ref)
         lat.set(f)

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_helpers import err_metric, lattice, need_gpu, noisy_state, note
+from gpu_helpers import LAYOUTS, err_metric, lattice, need_gpu, noisy_state, note
 from paper_1703_00185_amd import inputs, lbm
 
 pytestmark = pytest.mark.gpu
@@ -61,12 +61,13 @@ def test_fp32_bc_bit_exact(lx, ly):
     assert np.array_equal(got, oracle.stored(oracle.bc(f, ns.t_bottom, ns.t_top), "fp32"))
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("path", [lbm.LBM_PATH_SEPARATE, lbm.LBM_PATH_FUSED])
 @pytest.mark.parametrize("lx,ly", SIZES)
-def test_fp32_step_within_one_ulp(lx, ly, path):
+def test_fp32_step_within_one_ulp(lx, ly, path, layout):
     ns = inputs.rt_config(lx, ly)
     f = _fp32_state(3, lx, ly)
-    with lattice(ns, path=path, storage=lbm.LBM_FP32) as lat:
+    with lattice(ns, path=path, storage=lbm.LBM_FP32, layout=layout) as lat:
         lat.set(f)
         lat.step(1)
         got = lat.get()

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_helpers import FP64_TOL, err_metric, lattice, need_gpu
+from gpu_helpers import FP64_TOL, LAYOUTS, err_metric, lattice, need_gpu
 from paper_1703_00185_amd import inputs, lbm
 
 pytestmark = pytest.mark.gpu
@@ -16,14 +16,15 @@ def _gpu():
     need_gpu()
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("storage", [lbm.LBM_FP64, lbm.LBM_FP32])
 @pytest.mark.parametrize("lx,ly", [(3, 6), (6, 12), (7, 20), (37, 70), (64, 128), (130, 257)])
-def test_regions_equal_fused(lx, ly, storage):
+def test_regions_equal_fused(lx, ly, storage, layout):
     ns = inputs.rt_config(lx, ly)
     rt = inputs.rt_perturbation(2, ly)
     out = []
     for path in (lbm.LBM_PATH_FUSED, lbm.LBM_PATH_REGIONS):
-        with lattice(ns, path=path, storage=storage) as lat:
+        with lattice(ns, path=path, storage=storage, layout=layout) as lat:
             lat.init_rt(rt)
             lat.step(9)
             out.append(lat.get())
