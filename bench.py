@@ -202,6 +202,8 @@ def main() -> int:
     ap.add_argument("--layout", choices=["column", "planar"], default="column",
                     help="population layout of the timed paths (planar is also timed for comparison)")
     ap.add_argument("--no-separate", action="store_true", help="time the fused path only")
+    ap.add_argument("--no-layout-compare", action="store_true",
+                    help="skip the fused run in the other population layout")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-gib", type=float, default=2.0,
@@ -244,14 +246,16 @@ def main() -> int:
         log(f"non-finite populations after the run: {cons[4]}")
         return 1
 
-    other = "planar" if args.layout == "column" else "column"
-    log(f"fused path, {other} layout {lx}x{ly}: {args.warmup} warmup + {args.steps} timed steps")
-    w5, k5, _, _ = time_path(lbm, ns, rt, lbm.LBM_PATH_FUSED, args.steps, args.warmup,
-                             dict(extra, layout=lbm.LBM_LAYOUT_COLUMN + lbm.LBM_LAYOUT_PLANAR - layout_kind))
-    other_layout = {"layout": other, "mlups": sites * args.steps / w5 / 1e6,
-                    "ms_per_step": w5 / args.steps * 1e3, "kernels": kernel_bandwidth(k5, sites, lx, ly)}
-    log(f"{other} layout: {other_layout['mlups']:.1f} MLUPS, "
-        f"fused kernel {other_layout['kernels']['fused']['gbs']:.0f} GB/s")
+    other_layout = None
+    if not args.no_layout_compare:
+        other = "planar" if args.layout == "column" else "column"
+        log(f"fused path, {other} layout {lx}x{ly}: {args.warmup} warmup + {args.steps} timed steps")
+        w5, k5, _, _ = time_path(lbm, ns, rt, lbm.LBM_PATH_FUSED, args.steps, args.warmup,
+                                 dict(extra, layout=lbm.LBM_LAYOUT_COLUMN + lbm.LBM_LAYOUT_PLANAR - layout_kind))
+        other_layout = {"layout": other, "mlups": sites * args.steps / w5 / 1e6,
+                        "ms_per_step": w5 / args.steps * 1e3, "kernels": kernel_bandwidth(k5, sites, lx, ly)}
+        log(f"{other} layout: {other_layout['mlups']:.1f} MLUPS, "
+            f"fused kernel {other_layout['kernels']['fused']['gbs']:.0f} GB/s")
 
     separate = None
     if not args.no_separate:
@@ -304,7 +308,7 @@ def main() -> int:
         "config": {"workload": f"rayleigh_taylor_{lx}x{ly}_fp64", "lx": lx, "ly": ly,
                    "path": "fused", "storage": "fp64", "layout": {
                        "kind": args.layout, "nx": layout[0], "ny_pitch": layout[1],
-                       "pstride": layout[2], "cstride": layout[3], "block": args.block or 256}},
+                       "pstride": layout[2], "cstride": layout[3], "block": layout[5]}},
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kern, "separate": separate,
         "bandwidth_probe": copy, "reduced_storage": reduced, "regions": regions,
         "other_layout": other_layout,

@@ -113,7 +113,9 @@ typedef struct {
   int32_t path;      /* lbm_path used by lbm_step */
   int32_t layout;    /* lbm_layout_kind */
   int32_t block;     /* work-group size of the lattice kernels: 64, 128,
-                        256, 512 or 1024; 0 selects the default (256) */
+                        256, 512 or 1024; 0 selects the default: 512
+                        (FP64), 256 (FP32), 128 (FP16DEV), lowered to the
+                        smallest power of two >= Ly when that is less */
   int32_t ny_pad;    /* extra elements in the row pitch NY; < 0 default */
   int64_t stride_pad; /* extra elements on the outer stride (cstride for
                          the column layout, pstride for the planar one);
@@ -222,8 +224,8 @@ int lbm_read_timing(lbm_handle *h, double ms[LBM_NPHASES], int64_t count[LBM_NPH
 /* Geometry of the bound lattice: out[0] columns NX = Lx + 6 (3 halo
  * columns each side), out[1] row pitch NY (elements), out[2] pstride and
  * out[3] cstride (elements; element (l, X, y) at l pstride + X cstride + y),
- * out[4] bytes of one lattice copy. */
-int lbm_layout(const lbm_handle *h, int64_t out[5]);
+ * out[4] bytes of one lattice copy, out[5] work-group size in use. */
+int lbm_layout(const lbm_handle *h, int64_t out[6]);
 
 /* Model constants as the library uses them (host only, no GPU): hops
  * e[37][2], opposite index opp[37], weights w[37], velocity scale r.  Any

@@ -228,8 +228,8 @@ def lbm_read_timing(h):
 
 
 def lbm_layout(h):
-    """(NX, NY, pstride, cstride, bytes of one lattice copy)."""
-    out = np.zeros(5, dtype=np.int64)
+    """(NX, NY, pstride, cstride, bytes of one lattice copy, work-group size)."""
+    out = np.zeros(6, dtype=np.int64)
     _check(load().lbm_layout(h, _ptr(out)), h)
     return tuple(int(v) for v in out)
 

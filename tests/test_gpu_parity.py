@@ -37,7 +37,7 @@ def test_init_rt_matches_oracle(lx, ly, layout):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-@pytest.mark.parametrize("block", [64, 256, 1024])
+@pytest.mark.parametrize("block", [64, 128, 256, 512, 1024])
 @pytest.mark.parametrize("lx,ly", SIZES)
 def test_propagate_bit_exact(lx, ly, block, layout):
     f = 1.0 + inputs.noise(lx * 1000 + ly, (37, lx, ly), 0.3)
@@ -77,7 +77,7 @@ def test_collide_matches_oracle(lx, ly, tau, gy, layout):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-@pytest.mark.parametrize("block", [64, 256, 1024])
+@pytest.mark.parametrize("block", [64, 128, 256, 512, 1024])
 @pytest.mark.parametrize("lx,ly", SIZES)
 def test_fused_phase_matches_oracle_step(lx, ly, block, layout):
     ns = inputs.rt_config(lx, ly)
@@ -158,6 +158,7 @@ def test_layout_strides_reported(lx, ly, ny_pad, stride_pad):
     with lattice(ns, layout=lbm.LBM_LAYOUT_COLUMN, ny_pad=ny_pad, stride_pad=stride_pad) as lat:
         assert lat.layout()[:4] == (nx, ny, ny, 37 * ny + pad)
         assert lat.layout()[4] == -(-nx * (37 * ny + pad) * 8 // 256) * 256
+        assert lat.layout()[5] == min(512, max(64, 1 << (ly - 1).bit_length()))
     with lattice(ns, layout=lbm.LBM_LAYOUT_PLANAR, ny_pad=ny_pad, stride_pad=stride_pad) as lat:
         plane = -(-nx * ny // 64) * 64 + pad
         assert lat.layout()[:4] == (nx, ny, plane, ny)
@@ -351,3 +352,15 @@ def test_bandwidth_probe_rejects_bad_arguments():
         lbm.lbm_probe_bandwidth(0, buf.data_ptr() + 8, buf.data_ptr(), 2048, 0, st)
     with pytest.raises(lbm.LbmError):
         lbm.lbm_probe_bandwidth(0, buf.data_ptr(), buf.data_ptr(), 1024, 0, st)
+
+
+@pytest.mark.parametrize("storage,ly,want", [
+    (lbm.LBM_FP64, 8192, 512), (lbm.LBM_FP32, 8192, 256), (lbm.LBM_FP16DEV, 8192, 128),
+    (lbm.LBM_FP64, 300, 512), (lbm.LBM_FP64, 200, 256), (lbm.LBM_FP64, 128, 128), (lbm.LBM_FP64, 6, 64),
+    (lbm.LBM_FP32, 100, 128),
+])
+def test_default_work_group_size(storage, ly, want):
+    with lattice(inputs.rt_config(8, ly), storage=storage) as lat:
+        assert lat.layout()[5] == want
+    with lattice(inputs.rt_config(8, ly), storage=storage, block=1024) as lat:
+        assert lat.layout()[5] == 1024
