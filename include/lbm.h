@@ -270,9 +270,10 @@ int lbm_probe_bandwidth(int32_t mode, const void *src, void *dst, size_t bytes, 
  * ---------------------------------------------------------------------- */
 typedef struct lbm_engine lbm_engine;
 
-/* Engine schedules (how work-groups of the persistent grid take tiles):
- * CHUNKED = one contiguous run of tiles per work-group; STRIDED = tiles
- * dealt round-robin.  A tile is `block` rows of one column of one lattice. */
+/* Engine schedules (how the persistent grid takes tiles): CHUNKED = one
+ * contiguous run of tiles per work-group, dealt to its wavefronts in turn;
+ * STRIDED = tiles dealt round-robin over all wavefronts.  A tile is one
+ * wavefront: 64 rows of one column of one lattice. */
 typedef enum { LBM_SCHED_CHUNKED = 0, LBM_SCHED_STRIDED = 1 } lbm_schedule;
 
 /* Bytes of device memory for an engine with max_slots lattices; 0 if
@@ -303,15 +304,16 @@ int lbm_engine_step(lbm_engine *e, int32_t n);
  * -1 for a free slot; may be NULL).  Finished lattices leave the tile table. */
 int lbm_engine_status(lbm_engine *e, int32_t *steps_left);
 
-/* Tiling: block (64, 128, 256, 512 rows per tile), persistent groups, and
- * lbm_schedule.  set_tiling rebuilds the step graph. */
+/* Tiling: block (work-group size 64, 128, 256 or 512: 1 to 8 wavefronts),
+ * persistent groups, and lbm_schedule.  set_tiling rebuilds the step
+ * graph. */
 int lbm_engine_set_tiling(lbm_engine *e, int32_t block, int32_t groups, int32_t schedule);
 int lbm_engine_get_tiling(const lbm_engine *e, int32_t out[3]);
 
 /* Autotune the tiling on the current lattices: times `reps` step launches
  * (without advancing any lattice: each launch rewrites the idle buffer from
  * the current one) for every block in {64,128,256,512}, groups in
- * {2,4,...,256} x compute units and both schedules; keeps the fastest.
+ * {2,4,...,1024} x compute units and both schedules; keeps the fastest.
  * out[3] = chosen (block, groups, schedule), *best_ms = its time per step
  * (either may be NULL).  Errors: ESTATE (no active lattice), EDEVICE. */
 int lbm_engine_tune(lbm_engine *e, int32_t reps, int32_t out[3], double *best_ms);

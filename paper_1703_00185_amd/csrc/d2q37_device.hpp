@@ -198,7 +198,9 @@ __device__ __forceinline__ void collide_site(double (&f)[NPOP], const CollidePar
 }
 
 // bc of one wall-row site: rho = f_0 + ... + f_36 (left fold), f_l = rho K_l.
-__device__ __forceinline__ void thermalise(double (&f)[NPOP], bool bottom, const WallParams& w) {
+// (WP: WallParams, possibly qualified with an address space.)
+template <class WP>
+__device__ __forceinline__ void thermalise(double (&f)[NPOP], bool bottom, const WP& w) {
   double rho = f[0];
 #pragma unroll
   for (int l = 1; l < NPOP; ++l) rho = rho + f[l];

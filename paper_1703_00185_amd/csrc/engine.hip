@@ -3,14 +3,18 @@
 // wrapping the source column), and a small kernel advances each lattice's
 // double buffer and step count.
 //
-// Work decomposition: a tile is BLOCK consecutive rows of one column of one
-// lattice; the tiles of all active lattices form one index space, in the
-// order of the active-slot table.  The grid is persistent (a fixed number
-// of work-groups).  CHUNKED gives each work-group one contiguous run of
-// tiles, so neighbouring tiles of a column run on the same CU and share the
-// cache lines the +-3-row pull straddles, and the lattice of the next tile
-// is found by stepping through the prefix table.  STRIDED deals tiles
-// round-robin and finds each tile's lattice by binary search.
+// Work decomposition: a tile is one wavefront, 64 consecutive rows of one
+// column of one lattice, so that lattices of any height waste only the
+// lanes of their last, ragged wavefront per column; the tiles of all
+// active lattices form one index space, in the order of the active-slot
+// table.  Each wavefront of a work-group takes its own tiles.  The grid is
+// persistent (a fixed number of work-groups).  CHUNKED gives each
+// work-group one contiguous run of tiles, dealt to its wavefronts in turn,
+// so neighbouring tiles of a column run on the same CU at the same time and
+// share the cache lines the +-3-row pull straddles; the lattice of the next
+// tile is found by stepping through the prefix table.  STRIDED deals tiles
+// round-robin over all wavefronts of the grid and finds each tile's lattice
+// by binary search.
 #pragma clang fp contract(off)
 
 #include "d2q37_device.hpp"
@@ -23,6 +27,12 @@ namespace {
 // know they are global memory; these pointers say so, which keeps loads
 // and stores in the global (not flat) address mode.
 #define GLOBAL_AS __attribute__((address_space(1)))
+// The slot table is read through the constant address space: no step
+// kernel writes it (the advance kernel and the host do, between launches),
+// and with a wavefront-uniform slot index every descriptor field is then a
+// scalar load into scalar registers instead of a vector load into VGPRs.
+#define CONST_AS __attribute__((address_space(4)))
+using SlotView = const CONST_AS SlotDesc;
 
 // Source column of population l for a tile at column x: periodic wrap.
 // x is uniform over the work-group, so this is scalar arithmetic.
@@ -34,7 +44,7 @@ __device__ __forceinline__ int wrap_col(int x, int ex, int lx) {
 }
 
 template <class C>
-__device__ __forceinline__ void gather_wrap_interior(const SlotDesc& d, const C& cd,
+__device__ __forceinline__ void gather_wrap_interior(SlotView& d, const C& cd,
                                                      const GLOBAL_AS typename C::S* src, int x, int y,
                                                      double (&f)[NPOP]) {
   using S = typename C::S;
@@ -49,7 +59,7 @@ __device__ __forceinline__ void gather_wrap_interior(const SlotDesc& d, const C&
 }
 
 template <class C>
-__device__ __forceinline__ void gather_wrap_wall(const SlotDesc& d, const C& cd,
+__device__ __forceinline__ void gather_wrap_wall(SlotView& d, const C& cd,
                                                  const GLOBAL_AS typename C::S* src, int x, int y,
                                                  double (&f)[NPOP]) {
 #pragma unroll
@@ -64,16 +74,17 @@ __device__ __forceinline__ void gather_wrap_wall(const SlotDesc& d, const C& cd,
   }
 }
 
-// One tile: rows yb*BLOCK .. of column x of lattice d, from buffer cur to
-// the other buffer.  Same arithmetic as the single-lattice fused kernel.
-template <class C, int BLOCK>
-__device__ __forceinline__ void step_tile(const SlotDesc& d, int x, int yb) {
+// One tile: rows yw*64 .. yw*64+63 of column x of lattice d, from buffer
+// cur to the other buffer.  Same arithmetic as the single-lattice fused
+// kernel.
+template <class C>
+__device__ __forceinline__ void step_tile(SlotView& d, int x, int yw) {
   using S = typename C::S;
   const C cd{nullptr, nullptr};
   const GLOBAL_AS S* src = (const GLOBAL_AS S*)(d.buf[d.cur]);
   GLOBAL_AS S* dst = (GLOBAL_AS S*)(d.buf[d.cur ^ 1]);
-  const int y = yb * BLOCK + static_cast<int>(threadIdx.x);
-  const int ywave = yb * BLOCK + static_cast<int>(threadIdx.x & ~(WAVE - 1));
+  const int ywave = yw * WAVE;
+  const int y = ywave + static_cast<int>(threadIdx.x & (WAVE - 1));
   double f[NPOP];
   const int interior = (ywave >= WALL_ROWS) && (ywave + WAVE <= d.ly - WALL_ROWS);
   if (__builtin_amdgcn_readfirstlane(interior)) {
@@ -83,7 +94,13 @@ __device__ __forceinline__ void step_tile(const SlotDesc& d, int x, int yb) {
     gather_wrap_wall(d, cd, src, x, yc, f);
     if (yc < WALL_ROWS || yc >= d.ly - WALL_ROWS) thermalise(f, yc < WALL_ROWS, d.wp);
   }
-  collide_site(f, d.cp);
+  CollideParams cp;  // field by field: no implicit copy out of the constant address space
+  cp.omega = d.cp.omega;
+  cp.one_minus_omega = d.cp.one_minus_omega;
+  cp.tgx = d.cp.tgx;
+  cp.tgy = d.cp.tgy;
+  cp.dtemp = d.cp.dtemp;
+  collide_site(f, cp);
   if (y < d.ly) {
     const unsigned site = static_cast<unsigned>(y);
     GLOBAL_AS S* col = dst + static_cast<long long>(x + HALO) * d.cstride;
@@ -94,50 +111,55 @@ __device__ __forceinline__ void step_tile(const SlotDesc& d, int x, int yb) {
   }
 }
 
-template <class C, int BLOCK>
-__device__ __forceinline__ void run_tile(const SlotDesc& d, int local) {
+template <class C>
+__device__ __forceinline__ void run_tile(SlotView& d, int local) {
   if (d.steps_left <= 0) return;
-  // the tile coordinates are uniform over the work-group: keep them (and
+  // the tile coordinates are uniform over the wavefront: keep them (and
   // every address derived from them) in scalar registers
-  const int x = __builtin_amdgcn_readfirstlane(local / d.ny_blocks);
-  const int yb = __builtin_amdgcn_readfirstlane(local - x * d.ny_blocks);
-  step_tile<C, BLOCK>(d, x, yb);
+  const int x = __builtin_amdgcn_readfirstlane(local / d.ny_waves);
+  const int yw = __builtin_amdgcn_readfirstlane(local - x * d.ny_waves);
+  step_tile<C>(d, x, yw);
+}
+
+// Last k in [0, n) with start[k] <= t (start[0] = 0 <= t).
+__device__ __forceinline__ int find_slot(const int* start, int n, int t) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
 }
 
 // One kernel per storage type (C): each walks the tile table of the
-// lattices of its type.
+// lattices of its type.  Wavefronts never synchronise with each other.
 template <class C, int BLOCK, int SCHED>
 __global__ void __launch_bounds__(BLOCK) engine_step_kernel(const SlotDesc* __restrict__ slots,
                                                             const int* __restrict__ table,
                                                             int max_slots) {
+  constexpr int W = BLOCK / WAVE;  // wavefronts per work-group
+  SlotView* cslots = (SlotView*)(slots);
   const int n = table[0];
   const int total = table[1];
   const int* order = table + 2;
   const int* start = table + 2 + max_slots;
   if (n <= 0 || total <= 0) return;
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / WAVE);
   if (SCHED == SCHED_CHUNKED) {
     const long long g = gridDim.x, b = blockIdx.x;
     const int t0 = static_cast<int>(total * b / g);
     const int t1 = static_cast<int>(total * (b + 1) / g);
-    if (t0 >= t1) return;
-    int lo = 0, hi = n - 1;  // last k with start[k] <= t0
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (start[mid] <= t0) lo = mid; else hi = mid - 1;
-    }
-    int k = lo;
-    for (int t = t0; t < t1; ++t) {
+    if (t0 + wave >= t1) return;
+    int k = find_slot(start, n, t0 + wave);
+    for (int t = t0 + wave; t < t1; t += W) {
       while (t >= start[k + 1]) ++k;
-      run_tile<C, BLOCK>(slots[order[k]], t - start[k]);
+      run_tile<C>(cslots[order[k]], t - start[k]);
     }
   } else {
-    for (int t = blockIdx.x; t < total; t += gridDim.x) {
-      int lo = 0, hi = n - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (start[mid] <= t) lo = mid; else hi = mid - 1;
-      }
-      run_tile<C, BLOCK>(slots[order[lo]], t - start[lo]);
+    const int stride = static_cast<int>(gridDim.x) * W;
+    for (int t = static_cast<int>(blockIdx.x) * W + wave; t < total; t += stride) {
+      const int k = find_slot(start, n, t);
+      run_tile<C>(cslots[order[k]], t - start[k]);
     }
   }
 }

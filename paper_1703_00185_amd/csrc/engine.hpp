@@ -18,7 +18,7 @@ struct SlotDesc {
   long long cstride;  // elements between columns
   int storage;      // STORAGE_F64 or STORAGE_F32
   int lx, ly;       // lattice size
-  int ny_blocks;    // ceil(ly / engine block)
+  int ny_waves;     // wavefront tiles per column: ceil(ly / 64)
   int cur;          // buffer holding the current populations
   int steps_left;   // steps still to run; 0 = finished (not stepped)
   int pad;

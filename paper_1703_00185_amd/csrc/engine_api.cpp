@@ -86,10 +86,11 @@ int upload_table(lbm_engine* e) {
       if (!e->handles[s] || e->steps_left[s] <= 0 || e->slots[s].storage != storage) continue;
       t[2 + n] = s;
       t[2 + m + n] = static_cast<int>(total);
-      total += static_cast<long long>(e->slots[s].lx) * e->slots[s].ny_blocks;
+      total += static_cast<long long>(e->slots[s].lx) * e->slots[s].ny_waves;
       ++n;
     }
-    if (total >= (1LL << 31)) return efail(e, LBM_EINVAL, "too many tiles in the engine");
+    // < 2^30 keeps every tile index plus a grid stride (< 2^23) inside int
+    if (total >= (1LL << 30)) return efail(e, LBM_EINVAL, "too many tiles in the engine");
     t[0] = n;
     t[1] = static_cast<int>(total);
     t[2 + m + n] = static_cast<int>(total);
@@ -100,13 +101,11 @@ int upload_table(lbm_engine* e) {
   return LBM_OK;
 }
 
-// Recompute the per-slot tile rows for the engine's work-group size and
-// upload every occupied slot (cur and steps_left as last known).
+// Upload every occupied slot (cur and steps_left as last known).
 int upload_slots(lbm_engine* e) {
   for (int s = 0; s < e->max_slots; ++s) {
     if (!e->handles[s]) continue;
     SlotDesc& d = e->slots[s];
-    d.ny_blocks = (d.ly + e->block - 1) / e->block;
     d.steps_left = e->steps_left[s];
     d.cur = e->handles[s]->cur;
     ENG_HIP(e, hipMemcpyAsync(e->d_slots + s, &d, sizeof(SlotDesc), hipMemcpyHostToDevice, e->stream));
@@ -309,7 +308,7 @@ int lbm_engine_add(lbm_engine* e, lbm_handle* h, int32_t steps, int32_t* slot) {
   d.storage = h->geo.storage;
   d.lx = h->geo.lx;
   d.ly = h->geo.ly;
-  d.ny_blocks = (d.ly + e->block - 1) / e->block;
+  d.ny_waves = (d.ly + 63) / 64;
   d.cur = h->cur;
   d.steps_left = steps;
   d.cp = h->cp;
@@ -388,7 +387,7 @@ int lbm_engine_tune(lbm_engine* e, int32_t reps, int32_t out[3], double* best_ms
   int best[3] = {e->block, e->groups, e->schedule};
   float best_t = 1e30f;
   const int blocks[] = {64, 128, 256, 512};
-  const int per_cu[] = {2, 4, 8, 16, 32, 64, 128, 256};
+  const int per_cu[] = {2, 4, 8, 16, 32, 64, 128, 256, 512, 1024};
   for (int blk : blocks) {
     e->block = blk;
     rc = upload_slots(e);
