@@ -51,29 +51,41 @@ __device__ __forceinline__ long long run_of(const Geometry& g, int l, int X) {
   return static_cast<long long>(l) * g.pstride + static_cast<long long>(X) * g.cstride;
 }
 
-// Pull gather of Eq. (10): f_l(x, y) <- f_l(x - e_lx, y - e_ly).  Columns
-// x - e_lx < 0 or >= Lx read the halo columns filled by pbc.  Interior
-// form, for a column x uniform over the work-group: the 37 source runs
-// start at uniform (scalar) addresses and all loads share the lane's byte
-// offset.
-template <class C>
+// Stored column X of the source of a pull from column x by e_x: with WRAP
+// the periodic image inside the lattice (x - e_x taken mod Lx; one
+// correction suffices since |e_x| <= 3 <= Lx), else x - e_x itself, whose
+// columns beyond the lattice are the halo columns filled by pbc.
+template <bool WRAP>
+__device__ __forceinline__ int source_column(const Geometry& g, int x, int ex) {
+  int xs = x - ex;
+  if (WRAP) {
+    if (xs < 0) xs += g.lx;
+    else if (xs >= g.lx) xs -= g.lx;
+  }
+  return xs + HALO;
+}
+
+// Pull gather of Eq. (10): f_l(x, y) <- f_l(x - e_lx, y - e_ly), periodic
+// in x.  Interior form, for a column x uniform over the work-group: the 37
+// source runs start at uniform (scalar) addresses and all loads share the
+// lane's byte offset.
+template <bool WRAP, class C>
 __device__ __forceinline__ void gather_interior(const Geometry& g, const C& cd,
                                                 const typename C::S* __restrict__ src, int x, int y,
                                                 double (&f)[NPOP]) {
   using S = typename C::S;
   const unsigned off = static_cast<unsigned>(y) * static_cast<unsigned>(sizeof(S));
-  const S* col = src + static_cast<long long>(x + HALO) * g.cstride;
 #pragma unroll
   for (int l = 0; l < NPOP; ++l) {
-    const S* base = col + (static_cast<long long>(l) * g.pstride -
-                           (static_cast<long long>(EX[l]) * g.cstride + EY[l]));
+    const S* base = src + (static_cast<long long>(source_column<WRAP>(g, x, EX[l])) * g.cstride +
+                           static_cast<long long>(l) * g.pstride - EY[l]);
     f[l] = cd.dec(ld(base, off), l, y - EY[l]);
   }
 }
 
 // General form, for wavefronts touching the walls: a source row beyond a
 // wall is replaced by the opposite population of the same site.
-template <class C>
+template <bool WRAP, class C>
 __device__ __forceinline__ void gather_wall(const Geometry& g, const C& cd,
                                             const typename C::S* __restrict__ src, int x, int y,
                                             double (&f)[NPOP]) {
@@ -82,7 +94,8 @@ __device__ __forceinline__ void gather_wall(const Geometry& g, const C& cd,
   for (int l = 0; l < NPOP; ++l) {
     const int ys = y - EY[l];
     const bool inside = (ys >= 0) && (ys < g.ly);
-    const long long idx = inside ? run_of(g, l, X - EX[l]) + ys : run_of(g, opp_of(l), X) + y;
+    const long long idx =
+        inside ? run_of(g, l, source_column<WRAP>(g, x, EX[l])) + ys : run_of(g, opp_of(l), X) + y;
     f[l] = cd.dec(src[idx], l, inside ? ys : y);  // opp(l) shares w_l
   }
 }
@@ -187,9 +200,9 @@ __global__ void __launch_bounds__(BLOCK) propagate_kernel(const typename C::S* _
   lane_site<BLOCK>(g, ColumnSet{0, g.lx, 0}, x, y, ywave);
   double f[NPOP];
   if (interior_wave(g, ywave)) {
-    gather_interior(g, cd, src, x, y, f);
+    gather_interior<false>(g, cd, src, x, y, f);
   } else {
-    gather_wall(g, cd, src, x, y < g.ly ? y : g.ly - 1, f);
+    gather_wall<false>(g, cd, src, x, y < g.ly ? y : g.ly - 1, f);
   }
   if (y < g.ly) store_column_site(g, cd, dst, x, y, f);
 }
@@ -227,8 +240,10 @@ __global__ void __launch_bounds__(BLOCK) collide_kernel(const typename C::S* __r
 
 // propagate + bc + collide in registers: one read and one write of every
 // population per step (the fusion the paper applies in Sec. 5, here on
-// every row, walls included, since bc is site-local).
-template <class C, int BLOCK>
+// every row, walls included, since bc is site-local).  WRAP: periodic x by
+// wrapping source columns (no halo read, so no pbc launch is needed);
+// else the halo columns are read.
+template <class C, int BLOCK, bool WRAP>
 __global__ void __launch_bounds__(BLOCK) fused_kernel(const typename C::S* __restrict__ src,
                                                       typename C::S* __restrict__ dst, Geometry g,
                                                       CollideParams c, WallParams w, ColumnSet cols) {
@@ -236,11 +251,17 @@ __global__ void __launch_bounds__(BLOCK) fused_kernel(const typename C::S* __res
   int x, y, ywave;
   lane_site<BLOCK>(g, cols, x, y, ywave);
   double f[NPOP];
+  // only the 3 + 3 edge columns pull across the periodic boundary; the
+  // column is uniform over the work-group, so this is one scalar branch
+  // and every other column runs the plain gather
+  const bool edge = WRAP && (x < HALO || x >= g.lx - HALO);
   if (interior_wave(g, ywave)) {
-    gather_interior(g, cd, src, x, y, f);
+    if (edge) gather_interior<true>(g, cd, src, x, y, f);
+    else gather_interior<false>(g, cd, src, x, y, f);
   } else {
     const int yc = y < g.ly ? y : g.ly - 1;
-    gather_wall(g, cd, src, x, yc, f);
+    if (edge) gather_wall<true>(g, cd, src, x, yc, f);
+    else gather_wall<false>(g, cd, src, x, yc, f);
     if (yc < WALL_ROWS || yc >= g.ly - WALL_ROWS) thermalise(f, yc < WALL_ROWS, w);
   }
   collide_site(f, c);
@@ -517,14 +538,19 @@ hipError_t launch_collide(const Geometry& g, const void* src, void* dst, const C
 }
 
 hipError_t launch_fused(const Geometry& g, const void* src, void* dst, const CollideParams& c,
-                        const WallParams& w, hipStream_t s, const ColumnSet* cols) {
+                        const WallParams& w, hipStream_t s, const ColumnSet* cols, bool wrap) {
   const ColumnSet all{0, g.lx, 0};
   const ColumnSet cs = cols ? *cols : all;
   const int ncols = cs.na + (cols ? cs.nb : 0);
   if (ncols <= 0) return hipSuccess;
   (void)hipGetLastError();
-  D2Q37_DISPATCH(g, hipLaunchKernelGGL((fused_kernel<C, BS>), dim3(ncols * g.ny_blocks), dim3(BS), 0,
-                                       s, static_cast<const S*>(src), static_cast<S*>(dst), g, c, w, cs));
+  if (wrap) {
+    D2Q37_DISPATCH(g, hipLaunchKernelGGL((fused_kernel<C, BS, true>), dim3(ncols * g.ny_blocks), dim3(BS),
+                                         0, s, static_cast<const S*>(src), static_cast<S*>(dst), g, c, w, cs));
+  } else {
+    D2Q37_DISPATCH(g, hipLaunchKernelGGL((fused_kernel<C, BS, false>), dim3(ncols * g.ny_blocks), dim3(BS),
+                                         0, s, static_cast<const S*>(src), static_cast<S*>(dst), g, c, w, cs));
+  }
   return hipGetLastError();
 }
 

@@ -135,10 +135,7 @@ int timed(lbm_handle* h, int phase, F&& launch) {
 // have no bulk and take the plain fused step.
 int region_step(lbm_handle* h) {
   const Geometry& g = h->geo;
-  if (g.lx < 7) {
-    int rc = run_phase(h, LBM_PHASE_PBC);
-    return rc == LBM_OK ? run_phase(h, LBM_PHASE_FUSED) : rc;
-  }
+  if (g.lx < 7) return run_phase(h, LBM_PHASE_FUSED);
   if (!h->side) {
     LBM_HIP(h, hipStreamCreate(&h->side));
     LBM_HIP(h, hipEventCreateWithFlags(&h->ev_ready, hipEventDisableTiming));
@@ -180,9 +177,10 @@ int run_phase(lbm_handle* h, int phase) {
       rc = timed(h, phase, [&] { return launch_collide(g, current(h), other(h), h->cp, h->stream); });
       if (rc == LBM_OK) h->cur ^= 1;
       break;
-    case LBM_PHASE_FUSED:
-      rc = timed(h, phase,
-                 [&] { return launch_fused(g, current(h), other(h), h->cp, h->wp, h->stream); });
+    case LBM_PHASE_FUSED:  // periodic x by wrapping: no halo read
+      rc = timed(h, phase, [&] {
+        return launch_fused(g, current(h), other(h), h->cp, h->wp, h->stream, nullptr, true);
+      });
       if (rc == LBM_OK) h->cur ^= 1;
       break;
     default:
@@ -325,15 +323,14 @@ int lbm_step(lbm_handle* h, int32_t n) {
       if (rc != LBM_OK) return rc;
       continue;
     }
-    int rc = run_phase(h, LBM_PHASE_PBC);
-    if (rc == LBM_OK) {
-      if (h->cfg.path == LBM_PATH_FUSED) {
-        rc = run_phase(h, LBM_PHASE_FUSED);
-      } else {
-        rc = run_phase(h, LBM_PHASE_PROPAGATE);
-        if (rc == LBM_OK) rc = run_phase(h, LBM_PHASE_BC);
-        if (rc == LBM_OK) rc = run_phase(h, LBM_PHASE_COLLIDE);
-      }
+    int rc;
+    if (h->cfg.path == LBM_PATH_FUSED) {
+      rc = run_phase(h, LBM_PHASE_FUSED);  // one launch: wraps x, needs no pbc
+    } else {
+      rc = run_phase(h, LBM_PHASE_PBC);
+      if (rc == LBM_OK) rc = run_phase(h, LBM_PHASE_PROPAGATE);
+      if (rc == LBM_OK) rc = run_phase(h, LBM_PHASE_BC);
+      if (rc == LBM_OK) rc = run_phase(h, LBM_PHASE_COLLIDE);
     }
     if (rc != LBM_OK) return rc;
   }
