@@ -199,7 +199,8 @@ int lbm_conservation(lbm_handle *h, double out[5]);
 
 /* Copy the current populations to / from a host array [37][Lx][Ly]
  * (checkpoint and restore; restore marks the state initialised), through
- * the storage codec, one plane at a time staged in the idle lattice copy.
+ * the storage codec, one population at a time staged in the idle lattice
+ * copy.
  * Synchronise the stream.  Deviation storage needs a reference first. */
 int lbm_get_populations(lbm_handle *h, double *host);
 int lbm_set_populations(lbm_handle *h, const double *host);

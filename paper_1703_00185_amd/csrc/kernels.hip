@@ -431,7 +431,7 @@ __global__ void __launch_bounds__(256) rt_reference_kernel(double* __restrict__ 
 // Host-array transfers through the codec: one population at a time
 // between binary64 values [x][y] and its stored runs.
 template <class C>
-__global__ void __launch_bounds__(256) encode_plane_kernel(const double* __restrict__ in,
+__global__ void __launch_bounds__(256) encode_population_kernel(const double* __restrict__ in,
                                                            typename C::S* __restrict__ f,
                                                            Geometry g, int l) {
   const C cd{g.ref, g.inv_ref};
@@ -444,7 +444,7 @@ __global__ void __launch_bounds__(256) encode_plane_kernel(const double* __restr
 }
 
 template <class C>
-__global__ void __launch_bounds__(256) decode_plane_kernel(const typename C::S* __restrict__ f,
+__global__ void __launch_bounds__(256) decode_population_kernel(const typename C::S* __restrict__ f,
                                                            double* __restrict__ out, Geometry g, int l) {
   const C cd{g.ref, g.inv_ref};
   const long long n = static_cast<long long>(g.lx) * g.ly;
@@ -608,18 +608,18 @@ hipError_t launch_rt_reference(const Geometry& g, double* ref, double* inv_ref, 
   return hipGetLastError();
 }
 
-hipError_t launch_encode_plane(const Geometry& g, const double* in, void* f, int l, hipStream_t s) {
+hipError_t launch_encode_population(const Geometry& g, const double* in, void* f, int l, hipStream_t s) {
   const long long n = static_cast<long long>(g.lx) * g.ly;
   (void)hipGetLastError();
-  D2Q37_STORAGE(g, hipLaunchKernelGGL(encode_plane_kernel<C>, dim3(static_cast<unsigned>((n + 255) / 256)),
+  D2Q37_STORAGE(g, hipLaunchKernelGGL(encode_population_kernel<C>, dim3(static_cast<unsigned>((n + 255) / 256)),
                                       dim3(256), 0, s, in, static_cast<S*>(f), g, l));
   return hipGetLastError();
 }
 
-hipError_t launch_decode_plane(const Geometry& g, const void* f, double* out, int l, hipStream_t s) {
+hipError_t launch_decode_population(const Geometry& g, const void* f, double* out, int l, hipStream_t s) {
   const long long n = static_cast<long long>(g.lx) * g.ly;
   (void)hipGetLastError();
-  D2Q37_STORAGE(g, hipLaunchKernelGGL(decode_plane_kernel<C>, dim3(static_cast<unsigned>((n + 255) / 256)),
+  D2Q37_STORAGE(g, hipLaunchKernelGGL(decode_population_kernel<C>, dim3(static_cast<unsigned>((n + 255) / 256)),
                                       dim3(256), 0, s, static_cast<const S*>(f), out, g, l));
   return hipGetLastError();
 }

@@ -74,7 +74,7 @@ constexpr int CONS_THREADS = 256;
 constexpr int CONS_FIELDS = 5;     // mass, jx, jy, energy, non-finite count
 
 // Launchers: enqueue one kernel on stream s; the population pointers
-// point to planes of the geometry's storage type.
+// point to lattice copies in the geometry's layout and storage type.
 hipError_t launch_pbc(const Geometry& g, void* f, hipStream_t s);
 hipError_t launch_propagate(const Geometry& g, const void* src, void* dst, hipStream_t s);
 hipError_t launch_bc(const Geometry& g, void* f, const WallParams& w, hipStream_t s);
@@ -94,8 +94,8 @@ hipError_t launch_get_sites(const Geometry& g, const void* f, const int* xy, int
 hipError_t launch_init_rt(const Geometry& g, void* f, const RtParams& p, hipStream_t s);
 hipError_t launch_rt_reference(const Geometry& g, double* ref, double* inv_ref, const RtParams& p,
                                hipStream_t s);
-hipError_t launch_encode_plane(const Geometry& g, const double* in, void* f, int l, hipStream_t s);
-hipError_t launch_decode_plane(const Geometry& g, const void* f, double* out, int l, hipStream_t s);
+hipError_t launch_encode_population(const Geometry& g, const double* in, void* f, int l, hipStream_t s);
+hipError_t launch_decode_population(const Geometry& g, const void* f, double* out, int l, hipStream_t s);
 
 // Copy probes (aligned copy, misaligned read / aligned write, aligned read /
 // misaligned write); n16 = bytes / 16, shift in doubles.

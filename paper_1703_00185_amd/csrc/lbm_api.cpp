@@ -92,7 +92,7 @@ int make_layout(const lbm_config* c, Layout* out, std::string* why) {
   out->geo = g;
   out->buf_bytes = static_cast<size_t>(round_up(elems * elem_bytes(g), 256));
   out->ref_bytes = g.storage == STORAGE_F16DEV ? static_cast<size_t>(round_up(8LL * c->ly, 256)) : 0;
-  // host transfers stage one plane of binary64 values in the idle copy
+  // host transfers stage one population ([lx][ly] binary64) in the idle copy
   if (static_cast<size_t>(8) * c->lx * c->ly > out->buf_bytes)
     return *why = "internal: staging does not fit", LBM_EINVAL;
   return LBM_OK;
@@ -445,7 +445,7 @@ int lbm_get_populations(lbm_handle* h, double* host) {
   const size_t n = static_cast<size_t>(g.lx) * g.ly;
   double* stage = scratch(h);
   for (int l = 0; l < NPOP; ++l) {
-    LBM_HIP(h, launch_decode_plane(g, current(h), stage, l, h->stream));
+    LBM_HIP(h, launch_decode_population(g, current(h), stage, l, h->stream));
     LBM_HIP(h, hipMemcpyAsync(host + static_cast<size_t>(l) * n, stage, n * sizeof(double),
                               hipMemcpyDeviceToHost, h->stream));
   }
@@ -466,7 +466,7 @@ int lbm_set_populations(lbm_handle* h, const double* host) {
   for (int l = 0; l < NPOP; ++l) {
     LBM_HIP(h, hipMemcpyAsync(stage, host + static_cast<size_t>(l) * n, n * sizeof(double),
                               hipMemcpyHostToDevice, h->stream));
-    LBM_HIP(h, launch_encode_plane(g, stage, current(h), l, h->stream));
+    LBM_HIP(h, launch_encode_population(g, stage, current(h), l, h->stream));
   }
   LBM_HIP(h, hipStreamSynchronize(h->stream));
   h->ready = true;
