@@ -1,15 +1,20 @@
 """Throughput of the D2Q37 thermal LBM step on one MI355X.
 
 Workload: the 2048 x 8192 Rayleigh-Taylor lattice in FP64 (16.8 M sites, 37
-populations each), seeded synthetic initial state, stepped with the fused
-path (pbc + one propagate/bc/collide kernel per step) and, beside it, the
-separate path (pbc, propagate, bc, collide).  A step is one update of the
-whole lattice.  Inputs are resident in HBM before the timed region.
+populations each), seeded synthetic initial state, column population
+layout, stepped with the fused path (one propagate/bc/collide kernel per
+step, periodic x by wrapping the source column).  A step is one update of
+the whole lattice.  Inputs are resident in HBM before the timed region.
+Beside it, for comparison: the same step in the planar layout, the
+separate path (pbc, propagate, bc, collide), FP32 and FP16-deviation
+storage, the region split, the 64 x 128 workload (plain and graph-replayed
+launches) and copy probes of the attainable bandwidth.
 
 Prints one JSON line: MLUPS of the fused path as `value`, the roofline of
 the dominant kernel (the fused kernel: 592 algorithmic bytes per site per
 launch, HBM-bound) from HIP events recorded around every launch inside the
-timed region, the separate path's per-kernel figures, and the FP64 CPU
+timed region, the measured HBM traffic of that kernel from the committed
+rocprofv3 counter summary, the other paths' figures, and the FP64 CPU
 oracle timed on a bounded sample on this host.
 """
 from __future__ import annotations
