@@ -33,8 +33,12 @@ struct Layout {
 // Default work-group size: the fastest measured on the 2048 x 8192 fused
 // step per storage type (512 for binary64, 256 for binary32, 128 for
 // binary16 deviations), but no more rows than the smallest power of two
-// covering ly, so that short columns do not idle most of the lanes.
-int default_block(int storage, int ly) {
+// covering ly, so that short columns do not idle most of the lanes.  A
+// lattice with fewer wavefronts than an MI355X has SIMDs (256 CUs x 4)
+// gets one-wavefront work-groups, spread over as many CUs as possible.
+int default_block(int storage, int lx, int ly) {
+  const long long waves = static_cast<long long>(lx) * ((ly + 63) / 64);
+  if (waves < 1024) return 64;
   const int pref = storage == LBM_FP64 ? 512 : storage == LBM_FP32 ? 256 : 128;
   int b = 64;
   while (b < pref && b < ly) b *= 2;
@@ -57,7 +61,7 @@ int make_layout(const lbm_config* c, Layout* out, std::string* why) {
     return *why = "layout must be LBM_LAYOUT_COLUMN or LBM_LAYOUT_PLANAR", LBM_EINVAL;
   if (c->path != LBM_PATH_SEPARATE && c->path != LBM_PATH_FUSED && c->path != LBM_PATH_REGIONS)
     return *why = "path must be LBM_PATH_SEPARATE, LBM_PATH_FUSED or LBM_PATH_REGIONS", LBM_EINVAL;
-  const int block = c->block == 0 ? default_block(c->storage, c->ly) : c->block;
+  const int block = c->block == 0 ? default_block(c->storage, c->lx, c->ly) : c->block;
   if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
     return *why = "block must be 0, 64, 128, 256, 512 or 1024", LBM_EINVAL;
   if (c->ny_pad > (1 << 20)) return *why = "ny_pad too large", LBM_EINVAL;

@@ -158,7 +158,7 @@ def test_layout_strides_reported(lx, ly, ny_pad, stride_pad):
     with lattice(ns, layout=lbm.LBM_LAYOUT_COLUMN, ny_pad=ny_pad, stride_pad=stride_pad) as lat:
         assert lat.layout()[:4] == (nx, ny, ny, 37 * ny + pad)
         assert lat.layout()[4] == -(-nx * (37 * ny + pad) * 8 // 256) * 256
-        assert lat.layout()[5] == min(512, max(64, 1 << (ly - 1).bit_length()))
+        assert lat.layout()[5] == 64  # fewer wavefronts than SIMDs
     with lattice(ns, layout=lbm.LBM_LAYOUT_PLANAR, ny_pad=ny_pad, stride_pad=stride_pad) as lat:
         plane = -(-nx * ny // 64) * 64 + pad
         assert lat.layout()[:4] == (nx, ny, plane, ny)
@@ -362,13 +362,15 @@ def test_bandwidth_probe_rejects_bad_arguments():
         lbm.lbm_probe_bandwidth(0, buf.data_ptr(), buf.data_ptr(), 1024, 0, st)
 
 
-@pytest.mark.parametrize("storage,ly,want", [
-    (lbm.LBM_FP64, 8192, 512), (lbm.LBM_FP32, 8192, 256), (lbm.LBM_FP16DEV, 8192, 128),
-    (lbm.LBM_FP64, 300, 512), (lbm.LBM_FP64, 200, 256), (lbm.LBM_FP64, 128, 128), (lbm.LBM_FP64, 6, 64),
-    (lbm.LBM_FP32, 100, 128),
+@pytest.mark.parametrize("storage,lx,ly,want", [
+    (lbm.LBM_FP64, 8, 8192, 512), (lbm.LBM_FP32, 8, 8192, 256), (lbm.LBM_FP16DEV, 8, 8192, 128),
+    (lbm.LBM_FP64, 256, 300, 512), (lbm.LBM_FP64, 256, 200, 256), (lbm.LBM_FP64, 512, 128, 128),
+    (lbm.LBM_FP32, 1024, 100, 128), (lbm.LBM_FP64, 1024, 6, 64),
+    # fewer wavefronts (lx * ceil(ly / 64)) than the 1024 SIMDs: one-wavefront groups
+    (lbm.LBM_FP64, 64, 128, 64), (lbm.LBM_FP64, 8, 300, 64), (lbm.LBM_FP32, 127, 512, 64),
 ])
-def test_default_work_group_size(storage, ly, want):
-    with lattice(inputs.rt_config(8, ly), storage=storage) as lat:
+def test_default_work_group_size(storage, lx, ly, want):
+    with lattice(inputs.rt_config(lx, ly), storage=storage) as lat:
         assert lat.layout()[5] == want
-    with lattice(inputs.rt_config(8, ly), storage=storage, block=1024) as lat:
+    with lattice(inputs.rt_config(lx, ly), storage=storage, block=1024) as lat:
         assert lat.layout()[5] == 1024
