@@ -8,7 +8,10 @@ the whole lattice.  Inputs are resident in HBM before the timed region.
 Beside it, for comparison: the same step in the planar layout, the
 separate path (pbc, propagate, bc, collide), FP32 and FP16-deviation
 storage, the region split, the 64 x 128 workload (plain and graph-replayed
-launches) and copy probes of the attainable bandwidth.
+launches), copy probes of the attainable bandwidth, and a bounded sample
+of the serving workload (Poisson arrivals of uneven FP64/FP32 requests
+stepped together by the ensemble engine) for the p50/p99 completion
+latency against a one-request-at-a-time FP64 server.
 
 Prints one JSON line: MLUPS of the fused path as `value`, the roofline of
 the dominant kernel (the fused kernel: 592 algorithmic bytes per site per
@@ -211,6 +214,8 @@ def main() -> int:
                     help="skip the fused run in the other population layout")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests of the bounded serving sample (p50/p99 latency); 0 skips it")
     ap.add_argument("--copy-gib", type=float, default=2.0,
                     help="size of the plain-copy reference (read GiB = write GiB)")
     args = ap.parse_args()
@@ -293,6 +298,19 @@ def main() -> int:
     small = small_lattice(lbm, inputs)
     log("64x128: " + ", ".join(f"{k} {v['us_per_step']:.1f} us/step" for k, v in small.items()))
 
+    serving = None
+    if args.serve_requests > 0:
+        from paper_1703_00185_amd.serve import serve_workload
+        log(f"serving sample: {args.serve_requests} requests through the ensemble engine")
+        serving = serve_workload(lbm, inputs, requests=args.serve_requests, log=log)
+        log(f"serving: {serving['served']['mlups']:.0f} MLUPS, p50 {serving['served']['latency_p50_s']:.2f} s, "
+            f"p99 {serving['served']['latency_p99_s']:.2f} s (one at a time FP64: p50 "
+            f"{serving['one_at_a_time_fp64']['latency_p50_s']:.2f} s, "
+            f"p99 {serving['one_at_a_time_fp64']['latency_p99_s']:.2f} s)")
+        if serving["identical_alone_and_in_mix"]["mismatches"]:
+            log("served results differ from the same requests run alone")
+            return 1
+
     fk = kern["fused"]
     traffic = measured_traffic(lx, ly, args.layout)
     roofline = {"bound": "hbm", "achieved": fk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -316,7 +334,7 @@ def main() -> int:
                        "pstride": layout[2], "cstride": layout[3], "block": layout[5]}},
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kern, "separate": separate,
         "bandwidth_probe": copy, "reduced_storage": reduced, "regions": regions,
-        "other_layout": other_layout,
+        "other_layout": other_layout, "ensemble_serving": serving,
         "small_lattice_64x128": small,
         "paper_equivalent_gflops": 6472 * sites * args.steps / wall / 1e9,
     }

@@ -156,34 +156,23 @@ def fifo_latencies(arrivals, service):
     return out
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--requests", type=int, default=5000)
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--load", type=float, default=0.8)
-    ap.add_argument("--budget-gb", type=float, default=200.0)
-    ap.add_argument("--max-slots", type=int, default=1024)
-    ap.add_argument("--chunk", type=int, default=25)
-    ap.add_argument("--check", type=int, default=12, help="served results recomputed alone")
-    args = ap.parse_args()
-
-    import torch
-    if not torch.cuda.is_available():
-        print("no GPU visible", file=sys.stderr)
-        return 1
-    from paper_1703_00185_amd import inputs, lbm
-
-    drawn = draw_requests(args.seed, args.requests)
+def serve_workload(lbm, inputs, requests: int = 5000, seed: int = 0, load: float = 0.8,
+                   budget_gb: float = 200.0, max_slots: int = 1024, chunk: int = 25,
+                   check: int = 12, log=None) -> dict:
+    """Run the serving workload on the current GPU; returns the result
+    record (the JSON object main() prints)."""
+    log = log or (lambda msg: print(msg, file=sys.stderr, flush=True))
+    drawn = draw_requests(seed, requests)
     work = np.array([lx * ly * st for lx, ly, st, _, _ in drawn], dtype=np.float64)
 
     # capacity: aggregate rate of the engine on a calibration batch of the mix
     cal = [d for d in drawn[:64]]
     cal_lats = []
     eng = lbm.Engine(max_slots=len(cal))
-    for lx, ly, _, sto, seed in cal:
+    for lx, ly, _, sto, s in cal:
         lat = lbm.Lattice(lbm.config_from(inputs.rt_config(lx, ly),
                                           storage=lbm.LBM_FP32 if sto else lbm.LBM_FP64))
-        lat.init_rt(inputs.rt_perturbation(seed, ly))
+        lat.init_rt(inputs.rt_perturbation(s, ly))
         eng.add(lat, 1000)
         cal_lats.append(lat)
     (block, groups, sched), _ = eng.tune(reps=2)
@@ -197,25 +186,24 @@ def main() -> int:
     for lat in cal_lats:
         lat.close()
     capacity = cal_mlups * 1e6 / float(work.mean())       # requests per second
-    rate = args.load * capacity
-    arrivals = poisson_arrivals(args.seed, args.requests, rate)
-    reqs = [Request(i, float(arrivals[i]), lx, ly, st, sto, seed)
-            for i, (lx, ly, st, sto, seed) in enumerate(drawn)]
-    print(f"[serve] calibration {cal_mlups:.0f} MLUPS -> capacity {capacity:.2f} req/s, "
-          f"arrival rate {rate:.2f} req/s, {args.requests} requests, "
-          f"{work.sum() / 1e12:.2f} T site-updates", file=sys.stderr, flush=True)
+    rate = load * capacity
+    arrivals = poisson_arrivals(seed, requests, rate)
+    reqs = [Request(i, float(arrivals[i]), lx, ly, st, sto, s)
+            for i, (lx, ly, st, sto, s) in enumerate(drawn)]
+    log(f"[serve] calibration {cal_mlups:.0f} MLUPS -> capacity {capacity:.2f} req/s, "
+        f"arrival rate {rate:.2f} req/s, {requests} requests, "
+        f"{work.sum() / 1e12:.2f} T site-updates")
 
-    rng = np.random.default_rng(args.seed + 7)
+    rng = np.random.default_rng(seed + 7)
     small = [r.rid for r in reqs if r.lx * r.ly <= 65536]
-    keep = set(rng.choice(small, size=min(args.check, len(small)), replace=False).tolist()) if small else set()
-    srv = Server(lbm, inputs, int(args.budget_gb * 2**30), args.max_slots, args.chunk, keep)
+    keep = set(rng.choice(small, size=min(check, len(small)), replace=False).tolist()) if small else set()
+    srv = Server(lbm, inputs, int(budget_gb * 2**30), max_slots, chunk, keep)
     srv.engine.set_tiling(block, groups, sched)
     done, makespan, site_steps = srv.run(reqs)
     lat_served = [done[r.rid] - r.arrival for r in reqs]
     mlups = site_steps / makespan / 1e6
-    print(f"[serve] served {len(done)} requests in {makespan:.1f} s: {mlups:.0f} MLUPS, "
-          f"p50 {percentile(lat_served, 50):.2f} s, p99 {percentile(lat_served, 99):.2f} s",
-          file=sys.stderr, flush=True)
+    log(f"[serve] served {len(done)} requests in {makespan:.1f} s: {mlups:.0f} MLUPS, "
+        f"p50 {percentile(lat_served, 50):.2f} s, p99 {percentile(lat_served, 99):.2f} s")
 
     # identical alone and in the mix
     mismatches = 0
@@ -242,9 +230,9 @@ def main() -> int:
     lat_base = fifo_latencies([r.arrival for r in reqs], service)
     base_mlups = float(work.sum()) / max(sum(service), 1e-9) / 1e6
 
-    print(json.dumps({
-        "workload": f"{args.requests} Rayleigh-Taylor requests, 64x128..1024x4096 log-uniform, "
-                    f"100-5000 steps, FP64/FP32 50/50, Poisson arrivals at {args.load} of capacity",
+    return {
+        "workload": f"{requests} Rayleigh-Taylor requests, 64x128..1024x4096 log-uniform, "
+                    f"100-5000 steps, FP64/FP32 50/50, Poisson arrivals at {load} of capacity",
         "arrival_rate_per_s": rate, "capacity_per_s": capacity, "calibration_mlups": cal_mlups,
         "tiling": {"block": block, "groups": groups, "schedule": sched},
         "served": {"mlups": mlups, "makespan_s": makespan,
@@ -257,8 +245,30 @@ def main() -> int:
                                "service_rates_measured": {f"{k[0]}x{k[1]}": v for k, v in rates.items()},
                                "note": "FIFO single server, service times from measured FP64 rates"},
         "identical_alone_and_in_mix": {"checked": len(srv.kept), "mismatches": mismatches},
-    }), flush=True)
-    return 0 if mismatches == 0 else 1
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--requests", type=int, default=5000)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--load", type=float, default=0.8)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--max-slots", type=int, default=1024)
+    ap.add_argument("--chunk", type=int, default=25)
+    ap.add_argument("--check", type=int, default=12, help="served results recomputed alone")
+    args = ap.parse_args()
+
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    from paper_1703_00185_amd import inputs, lbm
+
+    out = serve_workload(lbm, inputs, args.requests, args.seed, args.load, args.budget_gb,
+                         args.max_slots, args.chunk, args.check)
+    print(json.dumps(out), flush=True)
+    return 0 if out["identical_alone_and_in_mix"]["mismatches"] == 0 else 1
 
 
 if __name__ == "__main__":
