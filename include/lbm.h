@@ -8,7 +8,10 @@
  *   - Sec. 2 (kernel list) and Sec. 4 (Single-GPU Implementation): per time
  *     step, pbc (periodic-x halo columns), propagate, bc (thermal walls on
  *     rows 0..2 and Ly-3..Ly-1) and collide, on a structure-of-arrays lattice
- *     stored column by column (y fastest) in two copies.
+ *     (each population of each column one contiguous run, y fastest; runs
+ *     ordered column-major or plane by plane, lbm_layout_kind) in two
+ *     copies.  The fused path does propagate + bc + collide in one kernel
+ *     and takes periodic x by wrapping instead of pbc.
  * Where the paper is silent the library takes these readings: the 37 hops
  * are the shells (0,0) (1,0) (1,1) (2,0) (2,1) (2,2) (3,0) (3,1) with all
  * images; the weights solve the isotropy conditions through order 8; the
@@ -169,8 +172,9 @@ int lbm_set_stream(lbm_handle *h, void *stream);
  * range, non-finite amp/phase/y_center), EDEVICE. */
 int lbm_init_rt(lbm_handle *h, const lbm_rt_params *rt);
 
-/* Advance n >= 0 time steps (Eq. 6; pbc, propagate, bc, collide per step).
- * Asynchronous.  Errors: EINVAL (n < 0), ESTATE (no state yet), EDEVICE. */
+/* Advance n >= 0 time steps (Eq. 6: propagate, bc, collide per step, x
+ * periodic) with the configured lbm_path.  Asynchronous.  Errors: EINVAL
+ * (n < 0), ESTATE (no state yet), EDEVICE. */
 int lbm_step(lbm_handle *h, int32_t n);
 
 /* Same steps as lbm_step, replayed from a HIP graph: the first call for a
