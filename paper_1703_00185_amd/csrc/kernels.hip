@@ -242,9 +242,11 @@ __global__ void __launch_bounds__(BLOCK) collide_kernel(const typename C::S* __r
 // population per step (the fusion the paper applies in Sec. 5, here on
 // every row, walls included, since bc is site-local).  WRAP: periodic x by
 // wrapping source columns (no halo read, so no pbc launch is needed);
-// else the halo columns are read.
+// else the halo columns are read.  Binary16-deviation lattices use the
+// non-wrapping form only: with both gathers it does not fit the register
+// bound of its codec (kMinWaves) without spilling.
 template <class C, int BLOCK, bool WRAP>
-__global__ void __launch_bounds__(BLOCK) fused_kernel(const typename C::S* __restrict__ src,
+__global__ void __launch_bounds__(BLOCK, C::kMinWaves) fused_kernel(const typename C::S* __restrict__ src,
                                                       typename C::S* __restrict__ dst, Geometry g,
                                                       CollideParams c, WallParams w, ColumnSet cols) {
   const C cd{g.ref, g.inv_ref};
@@ -545,8 +547,24 @@ hipError_t launch_fused(const Geometry& g, const void* src, void* dst, const Col
   if (ncols <= 0) return hipSuccess;
   (void)hipGetLastError();
   if (wrap) {
-    D2Q37_DISPATCH(g, hipLaunchKernelGGL((fused_kernel<C, BS, true>), dim3(ncols * g.ny_blocks), dim3(BS),
-                                         0, s, static_cast<const S*>(src), static_cast<S*>(dst), g, c, w, cs));
+    switch (g.storage) {  // binary64 and binary32 only (see fused_kernel)
+      case STORAGE_F64: {
+        using C = CodecF64;
+        using S = C::S;
+        D2Q37_BLOCKS(g, hipLaunchKernelGGL((fused_kernel<C, BS, true>), dim3(ncols * g.ny_blocks), dim3(BS),
+                                           0, s, static_cast<const S*>(src), static_cast<S*>(dst), g, c, w, cs));
+        break;
+      }
+      case STORAGE_F32: {
+        using C = CodecF32;
+        using S = C::S;
+        D2Q37_BLOCKS(g, hipLaunchKernelGGL((fused_kernel<C, BS, true>), dim3(ncols * g.ny_blocks), dim3(BS),
+                                           0, s, static_cast<const S*>(src), static_cast<S*>(dst), g, c, w, cs));
+        break;
+      }
+      default:
+        return hipErrorInvalidValue;
+    }
   } else {
     D2Q37_DISPATCH(g, hipLaunchKernelGGL((fused_kernel<C, BS, false>), dim3(ncols * g.ny_blocks), dim3(BS),
                                          0, s, static_cast<const S*>(src), static_cast<S*>(dst), g, c, w, cs));

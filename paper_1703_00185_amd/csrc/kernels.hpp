@@ -81,8 +81,9 @@ hipError_t launch_bc(const Geometry& g, void* f, const WallParams& w, hipStream_
 hipError_t launch_collide(const Geometry& g, const void* src, void* dst, const CollideParams& c,
                           hipStream_t s);
 // cols = nullptr: every column; else the two column ranges of *cols.
-// wrap: periodic x by wrapping source columns (reads no halo column);
-// else the halo columns written by pbc are read.
+// wrap: periodic x by wrapping source columns (reads no halo column;
+// binary64 and binary32 storage only); else the halo columns written by
+// pbc are read.
 hipError_t launch_fused(const Geometry& g, const void* src, void* dst, const CollideParams& c,
                         const WallParams& w, hipStream_t s, const ColumnSet* cols = nullptr,
                         bool wrap = false);

@@ -181,9 +181,10 @@ int run_phase(lbm_handle* h, int phase) {
       rc = timed(h, phase, [&] { return launch_collide(g, current(h), other(h), h->cp, h->stream); });
       if (rc == LBM_OK) h->cur ^= 1;
       break;
-    case LBM_PHASE_FUSED:  // periodic x by wrapping: no halo read
+    case LBM_PHASE_FUSED:  // periodic x by wrapping (binary16 deviations: halo read)
       rc = timed(h, phase, [&] {
-        return launch_fused(g, current(h), other(h), h->cp, h->wp, h->stream, nullptr, true);
+        return launch_fused(g, current(h), other(h), h->cp, h->wp, h->stream, nullptr,
+                            g.storage != STORAGE_F16DEV);
       });
       if (rc == LBM_OK) h->cur ^= 1;
       break;
@@ -329,7 +330,10 @@ int lbm_step(lbm_handle* h, int32_t n) {
     }
     int rc;
     if (h->cfg.path == LBM_PATH_FUSED) {
-      rc = run_phase(h, LBM_PHASE_FUSED);  // one launch: wraps x, needs no pbc
+      // one launch that wraps x; binary16-deviation lattices refresh the
+      // halo columns first and run the non-wrapping kernel
+      rc = h->geo.storage == STORAGE_F16DEV ? run_phase(h, LBM_PHASE_PBC) : LBM_OK;
+      if (rc == LBM_OK) rc = run_phase(h, LBM_PHASE_FUSED);
     } else {
       rc = run_phase(h, LBM_PHASE_PBC);
       if (rc == LBM_OK) rc = run_phase(h, LBM_PHASE_PROPAGATE);

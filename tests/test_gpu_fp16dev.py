@@ -124,3 +124,16 @@ def test_fp16dev_reference_validation():
     with lattice(ns) as lat:
         with pytest.raises(lbm.LbmError):
             lbm.lbm_set_reference(lat.h, np.ones(32))
+
+
+def test_fp16dev_fused_step_refreshes_halos_then_runs_one_kernel():
+    """Deviation lattices take pbc + the non-wrapping fused kernel per step
+    (the wrapping form does not fit that kernel's register bound)."""
+    ns = inputs.rt_config(64, 128)
+    with lattice(ns, storage=lbm.LBM_FP16DEV) as lat:
+        lat.init_rt(inputs.rt_perturbation(0, 128))
+        lbm.lbm_set_timing(lat.h, True)
+        lat.step(3)
+        ms, cnt = lbm.lbm_read_timing(lat.h)
+        lbm.lbm_set_timing(lat.h, False)
+    assert cnt.tolist() == [3, 0, 0, 0, 3, 0, 0]
