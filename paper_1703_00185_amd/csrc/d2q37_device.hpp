@@ -31,14 +31,29 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
 }
 
 // Raw element access at a byte offset from a wavefront-uniform base.
+// Binary16 elements go through a buffer descriptor built from the uniform
+// base (scalar instructions), so the per-lane offset is the only vector
+// operand and no 64-bit vector address is formed per access.
+constexpr int kBufferWord3 = 0x00020000;  // gfx9 raw buffer: 32-bit data format
 template <class S>
 __device__ __forceinline__ S ld(const S* base, unsigned byte_off) {
-  return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + byte_off);
+  if constexpr (sizeof(S) == 2) {
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<S*>(base), 0, 0x7fffffff, kBufferWord3);
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, byte_off, 0, 0));
+  } else {
+    return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + byte_off);
+  }
 }
 // Non-temporal store (streaming: no reuse expected from the caches).
 template <class S>
 __device__ __forceinline__ void st_nt(S* base, unsigned byte_off, S v) {
-  __builtin_nontemporal_store(v, reinterpret_cast<S*>(reinterpret_cast<char*>(base) + byte_off));
+  if constexpr (sizeof(S) == 2) {
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, 0, 0x7fffffff, kBufferWord3);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, byte_off, 0, 2);
+  } else {
+    __builtin_nontemporal_store(v, reinterpret_cast<S*>(reinterpret_cast<char*>(base) + byte_off));
+  }
 }
 
 // Population storage codecs.  Arithmetic is binary64 for every storage;
