@@ -30,29 +30,45 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
   return xcd * q + (xcd < r ? xcd : r) + idx;
 }
 
-// Raw element access at a byte offset from a wavefront-uniform base.
-// Binary16 elements go through a buffer descriptor built from the uniform
-// base (scalar instructions), so the per-lane offset is the only vector
-// operand and no 64-bit vector address is formed per access.
+// Raw element access at a byte offset from a wavefront-uniform base,
+// through a buffer descriptor built from that base (scalar instructions):
+// the per-lane offset is the only vector operand, so no 64-bit vector
+// address is formed per access (measured on the 2048 x 8192 fused step:
+// binary16 +8 %, binary32 +2 %, binary64 +1 %).  The descriptor's range
+// (2^31 - 1 bytes) is far above any offset used here (below one column
+// run).  Cache-policy operand: 0 default, 2 non-temporal.
 constexpr int kBufferWord3 = 0x00020000;  // gfx9 raw buffer: 32-bit data format
+constexpr int kNonTemporal = 2;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_at(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, 0x7fffffff, kBufferWord3);
+}
+
 template <class S>
 __device__ __forceinline__ S ld(const S* base, unsigned byte_off) {
+  const __amdgpu_buffer_rsrc_t r = buffer_at(base);
   if constexpr (sizeof(S) == 2) {
-    const __amdgpu_buffer_rsrc_t r =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<S*>(base), 0, 0x7fffffff, kBufferWord3);
     return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, byte_off, 0, 0));
+  } else if constexpr (sizeof(S) == 4) {
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
   } else {
-    return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + byte_off);
+    static_assert(sizeof(S) == 8, "2-, 4- or 8-byte elements");
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
   }
 }
+
 // Non-temporal store (streaming: no reuse expected from the caches).
 template <class S>
 __device__ __forceinline__ void st_nt(S* base, unsigned byte_off, S v) {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  const __amdgpu_buffer_rsrc_t r = buffer_at(base);
   if constexpr (sizeof(S) == 2) {
-    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, 0, 0x7fffffff, kBufferWord3);
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, byte_off, 0, 2);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, byte_off, 0, kNonTemporal);
+  } else if constexpr (sizeof(S) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, byte_off, 0, kNonTemporal);
   } else {
-    __builtin_nontemporal_store(v, reinterpret_cast<S*>(reinterpret_cast<char*>(base) + byte_off));
+    static_assert(sizeof(S) == 8, "2-, 4- or 8-byte elements");
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, byte_off, 0, kNonTemporal);
   }
 }
 
