@@ -168,3 +168,21 @@ def test_engine_argument_checks():
         eng.close()
         lat.close()
         f16.close()
+
+
+def test_engine_zero_steps_and_empty_engine():
+    """Stepping an empty engine, or any engine by zero steps, changes nothing."""
+    eng = lbm.Engine(max_slots=2)
+    lat, _ = _lattice(MIX[0], 0)
+    try:
+        eng.step(3)                  # no lattice yet
+        eng.status()
+        s = eng.add(lat, 5)
+        before = lat.get()
+        eng.step(0)
+        assert eng.status()[s] == 5
+        after = lat.get()
+    finally:
+        eng.close()
+        lat.close()
+    assert np.array_equal(before, after)

@@ -374,3 +374,18 @@ def test_default_work_group_size(storage, lx, ly, want):
         assert lat.layout()[5] == want
     with lattice(inputs.rt_config(lx, ly), storage=storage, block=1024) as lat:
         assert lat.layout()[5] == 1024
+
+
+@pytest.mark.parametrize("path", [lbm.LBM_PATH_SEPARATE, lbm.LBM_PATH_FUSED, lbm.LBM_PATH_REGIONS])
+def test_empty_requests_change_nothing(path):
+    """Zero steps (plain and captured) and an empty site list are no-ops."""
+    ns = inputs.rt_config(37, 70)
+    with lattice(ns, path=path) as lat:
+        lat.init_rt(inputs.rt_perturbation(4, 70))
+        before = lat.get()
+        lat.step(0)
+        lat.step_captured(0)
+        got = lat.sites(np.array([], dtype=np.int64), np.array([], dtype=np.int64))
+        after = lat.get()
+    assert got.shape == (37, 0)
+    assert np.array_equal(before, after)
