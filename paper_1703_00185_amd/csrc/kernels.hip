@@ -198,6 +198,7 @@ __global__ void __launch_bounds__(BLOCK) propagate_kernel(const typename C::S* _
   const C cd{g.ref, g.inv_ref};
   int x, y, ywave;
   lane_site<BLOCK>(g, ColumnSet{0, g.lx, 0}, x, y, ywave);
+  if (ywave >= g.ly) return;  // whole wavefront beyond the lattice (no barrier follows)
   double f[NPOP];
   if (interior_wave(g, ywave)) {
     gather_interior<false>(g, cd, src, x, y, f);
@@ -252,6 +253,7 @@ __global__ void __launch_bounds__(BLOCK, C::kMinWaves) fused_kernel(const typena
   const C cd{g.ref, g.inv_ref};
   int x, y, ywave;
   lane_site<BLOCK>(g, cols, x, y, ywave);
+  if (ywave >= g.ly) return;  // whole wavefront beyond the lattice (no barrier follows)
   double f[NPOP];
   // only the 3 + 3 edge columns pull across the periodic boundary; the
   // column is uniform over the work-group, so this is one scalar branch
