@@ -91,7 +91,7 @@ def test_isotropy_by_brute_force(order):
 
 
 def test_extended_precision_solution_satisfies_conditions():
-    """The 55-digit solution satisfies every moment condition to 1e-40."""
+    """The 60-digit solution satisfies every moment condition to 1e-40."""
     import mpmath as mp
     r_str, w_str = oracle.solve_isotropy()
     E, shell, _ = oracle.velocity_set()
