@@ -44,13 +44,15 @@ def test_regions_match_oracle_and_time_both_parts():
     assert err_metric(got, oracle.run(f0, ns, 4)) < FP64_TOL
 
 
+@pytest.mark.parametrize("storage", [lbm.LBM_FP64, lbm.LBM_FP32, lbm.LBM_FP16DEV])
 @pytest.mark.parametrize("path", [lbm.LBM_PATH_SEPARATE, lbm.LBM_PATH_FUSED, lbm.LBM_PATH_REGIONS])
-def test_captured_steps_equal_plain_steps(path):
+def test_captured_steps_equal_plain_steps(path, storage):
     """Graph-replayed steps (odd and even counts, both buffer parities,
-    replayed several times with eager work in between) equal plain steps."""
+    replayed several times with eager work in between) equal plain steps,
+    for every storage type (the deviation path adds a pbc launch)."""
     ns = inputs.rt_config(64, 128)
     rt = inputs.rt_perturbation(1, 128)
-    with lattice(ns, path=path) as a, lattice(ns, path=path) as b:
+    with lattice(ns, path=path, storage=storage) as a, lattice(ns, path=path, storage=storage) as b:
         a.init_rt(rt)
         b.init_rt(rt)
         for n in (3, 4, 3, 3, 4, 1):
