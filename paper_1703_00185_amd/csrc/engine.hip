@@ -14,7 +14,9 @@
 // share the cache lines the +-3-row pull straddles; the lattice of the next
 // tile is found by stepping through the prefix table.  STRIDED deals tiles
 // round-robin over all wavefronts of the grid and finds each tile's lattice
-// by binary search.
+// by binary search.  In both, work-group ids are renumbered so that each of
+// the 8 XCDs (which the hardware deals ids to round-robin, each with its
+// own L2) takes one contiguous share of the tiles.
 #pragma clang fp contract(off)
 
 #include "d2q37_device.hpp"
@@ -146,7 +148,9 @@ __global__ void __launch_bounds__(BLOCK) engine_step_kernel(const SlotDesc* __re
   if (n <= 0 || total <= 0) return;
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / WAVE);
   if (SCHED == SCHED_CHUNKED) {
-    const long long g = gridDim.x, b = blockIdx.x;
+    // each XCD takes one contiguous share of the tile runs
+    const long long g = gridDim.x;
+    const long long b = xcd_tile(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
     const int t0 = static_cast<int>(total * b / g);
     const int t1 = static_cast<int>(total * (b + 1) / g);
     if (t0 + wave >= t1) return;
@@ -157,7 +161,13 @@ __global__ void __launch_bounds__(BLOCK) engine_step_kernel(const SlotDesc* __re
     }
   } else {
     const int stride = static_cast<int>(gridDim.x) * W;
-    for (int t = static_cast<int>(blockIdx.x) * W + wave; t < total; t += stride) {
+    // renumber over the work-groups that have tiles in the first sweep, so
+    // that each XCD takes a contiguous share of them (all of them when the
+    // grid exceeds the tile count)
+    const int busy = min(static_cast<int>(gridDim.x), (total + W - 1) / W);
+    const int b = static_cast<int>(blockIdx.x) < busy ? xcd_tile(static_cast<int>(blockIdx.x), busy)
+                                                    : static_cast<int>(blockIdx.x);
+    for (int t = b * W + wave; t < total; t += stride) {
       const int k = find_slot(start, n, t);
       run_tile<C>(cslots[order[k]], t - start[k]);
     }
