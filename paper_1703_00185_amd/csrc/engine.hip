@@ -104,12 +104,12 @@ __device__ __forceinline__ void step_tile(SlotView& d, int x, int yw) {
   cp.dtemp = d.cp.dtemp;
   collide_site(f, cp);
   if (y < d.ly) {
-    const unsigned site = static_cast<unsigned>(y);
+    const unsigned off = static_cast<unsigned>(y) * static_cast<unsigned>(sizeof(S));
     GLOBAL_AS S* col = dst + static_cast<long long>(x + HALO) * d.cstride;
-    // non-temporal: every element is written once per step
+    // streaming stores: every element is written once per step
 #pragma unroll
     for (int l = 0; l < NPOP; ++l)
-      __builtin_nontemporal_store(cd.enc(f[l], l, y), &(col + static_cast<long long>(l) * d.pstride)[site]);
+      st_nt((S*)(col + static_cast<long long>(l) * d.pstride), off, cd.enc(f[l], l, y));
   }
 }
 
