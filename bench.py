@@ -15,8 +15,9 @@ latency against a one-request-at-a-time FP64 server.
 
 Prints one JSON line: MLUPS of the fused path as `value`, the roofline of
 the dominant kernel (the fused kernel: 592 algorithmic bytes per site per
-launch, HBM-bound) from HIP events recorded around every launch inside the
-timed region, the measured HBM traffic of that kernel from the committed
+launch, HBM-bound) from two HIP events on the lattice's stream bracketing
+the timed launches (one launch per step, so the span over the launch count
+is the average launch duration, gaps between launches included), the measured HBM traffic of that kernel from the committed
 rocprofv3 counter summary, the other paths' figures, and the FP64 CPU
 oracle timed on a bounded sample on this host.
 """
@@ -69,31 +70,67 @@ def measured_traffic(lx: int, ly: int, layout: str):
     return t.get("bytes_per_launch")
 
 
-def time_path(lbm, ns, rt, path: int, steps: int, warmup: int, extra: dict):
+def time_path(lbm, ns, rt, path: int, steps: int, warmup: int, extra: dict,
+              breakdown_steps: int = 0, graph_chunk: int = 0):
+    """Time `steps` steps of one path.  The timed region holds only the
+    step launches: no per-launch markers (they add a few microseconds per
+    launch, and cross-stream ones more); two HIP events on the lattice's
+    stream bracket it.  On a path with one launch per step the span over
+    the launch count is that kernel's average launch duration (gaps between
+    launches included).  With `breakdown_steps`, a separate run with a HIP
+    event pair around every launch gives the per-kernel breakdown; with
+    `graph_chunk`, the same steps are also replayed from a captured graph
+    of that many steps."""
     import torch
     cfg = lbm.config_from(ns, path=path, **extra)
     lat = lbm.Lattice(cfg)
     try:
         lat.init_rt(rt)
         lat.step(warmup)
-        torch.cuda.synchronize()
-        lbm.lbm_set_timing(lat.h, True)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        ev0.record(lat.stream)
         lat.step(steps)
+        ev1.record(lat.stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        ms, cnt = lbm.lbm_read_timing(lat.h)
-        lbm.lbm_set_timing(lat.h, False)
+        span_ms = ev0.elapsed_time(ev1)
+        kernels = {}
+        if breakdown_steps:
+            lbm.lbm_set_timing(lat.h, True)
+            lat.step(breakdown_steps)
+            ms, cnt = lbm.lbm_read_timing(lat.h)
+            lbm.lbm_set_timing(lat.h, False)
+            for p, name in enumerate(lbm.PHASE_NAMES):
+                if cnt[p]:
+                    kernels[name] = {"launches": int(cnt[p]), "avg_ms": float(ms[p] / cnt[p]),
+                                     "timing": f"HIP events around every launch, separate run of "
+                                               f"{breakdown_steps} steps"}
+        graph_wall = None
+        if graph_chunk:
+            reps = max(1, steps // graph_chunk)
+            lat.step_captured(graph_chunk)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                lat.step_captured(graph_chunk)
+            torch.cuda.synchronize()
+            graph_wall = (time.perf_counter() - t0) / (reps * graph_chunk)
         cons = lat.conservation()
         layout = lat.layout()
     finally:
         lat.close()
-    kernels = {}
-    for p, name in enumerate(lbm.PHASE_NAMES):
-        if cnt[p]:
-            kernels[name] = {"launches": int(cnt[p]), "avg_ms": float(ms[p] / cnt[p])}
-    return wall, kernels, cons, layout
+    return {"wall": wall, "span_ms": span_ms, "kernels": kernels, "cons": cons, "layout": layout,
+            "graph_s_per_step": graph_wall}
+
+
+def single_kernel(name: str, run: dict, steps: int) -> dict:
+    """Average launch duration of the one kernel a path launches per step,
+    from the events bracketing the timed region."""
+    return {name: {"launches": steps, "avg_ms": run["span_ms"] / steps,
+                   "timing": "two HIP events bracketing the timed launches"}}
 
 
 def probe_bandwidth(lbm, gib: float, reps: int = 10) -> dict:
@@ -236,6 +273,7 @@ def main() -> int:
 
     lx, ly = args.lx, args.ly
     sites = lx * ly
+    breakdown = min(args.steps, 200)  # steps of the per-launch timing runs
     ns = inputs.rt_config(lx, ly)
     rt = inputs.rt_perturbation(0, ly)
     layout_kind = lbm.LBM_LAYOUT_PLANAR if args.layout == "planar" else lbm.LBM_LAYOUT_COLUMN
@@ -247,8 +285,9 @@ def main() -> int:
         log(f"copy probe of {args.copy_gib} GiB: {copy['copy']['gbs']:.0f} GB/s; "
             f"mraw(+1) {copy['mraw']['1']:.0f}, armw(+1) {copy['armw']['1']:.0f} GB/s")
     log(f"fused path {lx}x{ly}: {args.warmup} warmup + {args.steps} timed steps")
-    wall, kern, cons, layout = time_path(lbm, ns, rt, lbm.LBM_PATH_FUSED, args.steps, args.warmup, extra)
-    kern = kernel_bandwidth(kern, sites, lx, ly)
+    run = time_path(lbm, ns, rt, lbm.LBM_PATH_FUSED, args.steps, args.warmup, extra)
+    wall, cons, layout = run["wall"], run["cons"], run["layout"]
+    kern = kernel_bandwidth(single_kernel("fused", run, args.steps), sites, lx, ly)
     mlups = sites * args.steps / wall / 1e6
     log(f"fused: {mlups:.1f} MLUPS, {wall / args.steps * 1e3:.3f} ms/step, "
         f"fused kernel {kern['fused']['avg_ms']:.3f} ms = {kern['fused']['gbs']:.0f} GB/s")
@@ -260,18 +299,22 @@ def main() -> int:
     if not args.no_layout_compare:
         other = "planar" if args.layout == "column" else "column"
         log(f"fused path, {other} layout {lx}x{ly}: {args.warmup} warmup + {args.steps} timed steps")
-        w5, k5, _, _ = time_path(lbm, ns, rt, lbm.LBM_PATH_FUSED, args.steps, args.warmup,
-                                 dict(extra, layout=lbm.LBM_LAYOUT_COLUMN + lbm.LBM_LAYOUT_PLANAR - layout_kind))
+        r5 = time_path(lbm, ns, rt, lbm.LBM_PATH_FUSED, args.steps, args.warmup,
+                       dict(extra, layout=lbm.LBM_LAYOUT_COLUMN + lbm.LBM_LAYOUT_PLANAR - layout_kind))
+        w5 = r5["wall"]
         other_layout = {"layout": other, "mlups": sites * args.steps / w5 / 1e6,
-                        "ms_per_step": w5 / args.steps * 1e3, "kernels": kernel_bandwidth(k5, sites, lx, ly)}
+                        "ms_per_step": w5 / args.steps * 1e3,
+                        "kernels": kernel_bandwidth(single_kernel("fused", r5, args.steps), sites, lx, ly)}
         log(f"{other} layout: {other_layout['mlups']:.1f} MLUPS, "
             f"fused kernel {other_layout['kernels']['fused']['gbs']:.0f} GB/s")
 
     separate = None
     if not args.no_separate:
         log(f"separate path {lx}x{ly}: {args.warmup} warmup + {args.steps} timed steps")
-        w2, k2, c2, _ = time_path(lbm, ns, rt, lbm.LBM_PATH_SEPARATE, args.steps, args.warmup, extra)
-        k2 = kernel_bandwidth(k2, sites, lx, ly)
+        r2 = time_path(lbm, ns, rt, lbm.LBM_PATH_SEPARATE, args.steps, args.warmup, extra,
+                       breakdown_steps=breakdown)
+        w2 = r2["wall"]
+        k2 = kernel_bandwidth(r2["kernels"], sites, lx, ly)
         separate = {"mlups": sites * args.steps / w2 / 1e6, "ms_per_step": w2 / args.steps * 1e3,
                     "kernels": k2}
         log(f"separate: {separate['mlups']:.1f} MLUPS")
@@ -279,8 +322,12 @@ def main() -> int:
     reduced = {}
     for name, storage, eb in (("fp32", lbm.LBM_FP32, 4), ("fp16dev", lbm.LBM_FP16DEV, 2)):
         log(f"fused path, {name} storage {lx}x{ly}: {args.warmup} warmup + {args.steps} timed steps")
-        w3, k3, c3, _ = time_path(lbm, ns, rt, lbm.LBM_PATH_FUSED, args.steps, args.warmup,
-                                  dict(extra, storage=storage))
+        # binary16 deviations launch pbc before the fused kernel: per-launch breakdown
+        r3 = time_path(lbm, ns, rt, lbm.LBM_PATH_FUSED, args.steps, args.warmup,
+                       dict(extra, storage=storage),
+                       breakdown_steps=breakdown if storage == lbm.LBM_FP16DEV else 0)
+        w3 = r3["wall"]
+        k3 = r3["kernels"] if storage == lbm.LBM_FP16DEV else single_kernel("fused", r3, args.steps)
         k3 = kernel_bandwidth(k3, sites, lx, ly, elem_bytes=eb)
         reduced[name] = {"mlups": sites * args.steps / w3 / 1e6, "ms_per_step": w3 / args.steps * 1e3,
                          "speedup_vs_fp64": wall / w3, "bytes_per_site": 2 * 37 * eb,
@@ -289,10 +336,15 @@ def main() -> int:
             f"fused kernel {k3['fused']['gbs']:.0f} GB/s")
 
     log(f"region path {lx}x{ly}: {args.warmup} warmup + {args.steps} timed steps")
-    w4, k4, _, _ = time_path(lbm, ns, rt, lbm.LBM_PATH_REGIONS, args.steps, args.warmup, extra)
+    r4 = time_path(lbm, ns, rt, lbm.LBM_PATH_REGIONS, args.steps, args.warmup, extra,
+                   breakdown_steps=breakdown, graph_chunk=50)
+    w4, g4 = r4["wall"], r4["graph_s_per_step"]
     regions = {"mlups": sites * args.steps / w4 / 1e6, "ms_per_step": w4 / args.steps * 1e3,
-               "kernels": kernel_bandwidth(k4, sites, lx, ly)}
-    log(f"regions: {regions['mlups']:.1f} MLUPS")
+               "graph_replayed": {"mlups": sites / g4 / 1e6, "ms_per_step": g4 * 1e3,
+                                  "graph_steps": 50},
+               "kernels": kernel_bandwidth(r4["kernels"], sites, lx, ly)}
+    log(f"regions: {regions['mlups']:.1f} MLUPS, graph-replayed "
+        f"{regions['graph_replayed']['mlups']:.1f} MLUPS")
 
     log("64x128 workload, 100 steps: plain and graph-captured launches")
     small = small_lattice(lbm, inputs)

@@ -74,10 +74,11 @@ typedef enum {
                             halo columns unused); LBM_FP16DEV lattices run
                             pbc, then the kernel reading the halo columns */
   LBM_PATH_REGIONS = 2   /* region split (Sec. 5, 1-D tiling): the fused
-                            kernel on the bulk columns 3..Lx-4 runs while
-                            pbc refreshes the halos on a second stream, then
-                            the 3 + 3 border columns run; same results as
-                            LBM_PATH_FUSED bit for bit */
+                            kernel on the bulk columns 3..Lx-4 runs on the
+                            bound stream while a second stream refreshes
+                            the halos (pbc) and steps the 3 + 3 border
+                            columns, ordered by events across steps only;
+                            same results as LBM_PATH_FUSED bit for bit */
 } lbm_path;
 
 /* Population layout in each lattice copy.  Columns X = 0 .. Lx+5 include

@@ -26,10 +26,12 @@ struct lbm_handle {
   d2q37::CollideParams cp{};
   d2q37::WallParams wp{};
   std::string err;
-  // region path: a second stream for pbc and the events that order it
+  // region path: a second stream for pbc and the border columns, and the
+  // events that order it against the bulk launches on the caller's stream
   hipStream_t side = nullptr;
-  hipEvent_t ev_ready = nullptr;
-  hipEvent_t ev_halo = nullptr;
+  hipEvent_t ev_ready = nullptr;   // caller's stream at the start of a step call
+  hipEvent_t ev_border = nullptr;  // last border launch
+  hipEvent_t ev_bulk = nullptr;    // last bulk launch
   // captured step sequences: (n, starting buffer) -> instantiated graph
   struct Captured {
     int n, cur, cur_after;  // steps, buffer at start and at the end

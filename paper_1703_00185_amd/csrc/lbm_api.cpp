@@ -133,33 +133,66 @@ int timed(lbm_handle* h, int phase, F&& launch) {
   return timed_on(h, phase, h->stream, launch);
 }
 
-// One step of the region path: pbc on the side stream, overlapped with the
-// fused kernel on the bulk columns (which read no halo), then the border
-// columns once the halos are in place.  Lattices narrower than 7 columns
-// have no bulk and take the plain fused step.
-int region_step(lbm_handle* h) {
+// The second stream and events of the region path (created outside any
+// stream capture).
+int ensure_side(lbm_handle* h) {
+  if (h->side) return LBM_OK;
+  LBM_HIP(h, hipStreamCreate(&h->side));
+  LBM_HIP(h, hipEventCreateWithFlags(&h->ev_ready, hipEventDisableTiming));
+  LBM_HIP(h, hipEventCreateWithFlags(&h->ev_border, hipEventDisableTiming));
+  LBM_HIP(h, hipEventCreateWithFlags(&h->ev_bulk, hipEventDisableTiming));
+  return LBM_OK;
+}
+
+// n steps of the region path.  Step k runs the fused kernel on the bulk
+// columns 3..Lx-4 (which pull from no halo) on the caller's stream, and pbc
+// followed by the 3 + 3 border columns on the side stream, concurrently.
+// Within a step the two write disjoint columns of the destination, so the
+// only orderings are across steps:
+//   bulk k   after border k-1 (it reads the border columns border k-1 wrote,
+//            and overwrites the bulk columns border k-1 read);
+//   border k after bulk k-1   (it reads the bulk columns next to the border
+//            that bulk k-1 wrote, and overwrites the border columns bulk
+//            k-1 read);
+//   pbc k    after border k-1 (it copies the border columns into the halo;
+//            same stream).
+// The first step of a call waits for everything already on the caller's
+// stream, and the caller's stream waits for the last border at the end, so
+// the call is ordered on the caller's stream as a whole.  Lattices narrower
+// than 7 columns have no bulk and take the plain fused step.
+int region_steps(lbm_handle* h, int32_t n) {
   const Geometry& g = h->geo;
-  if (g.lx < 7) return run_phase(h, LBM_PHASE_FUSED);
-  if (!h->side) {
-    LBM_HIP(h, hipStreamCreate(&h->side));
-    LBM_HIP(h, hipEventCreateWithFlags(&h->ev_ready, hipEventDisableTiming));
-    LBM_HIP(h, hipEventCreateWithFlags(&h->ev_halo, hipEventDisableTiming));
+  if (g.lx < 7) {
+    for (int32_t k = 0; k < n; ++k) {
+      const int rc = run_phase(h, LBM_PHASE_FUSED);
+      if (rc != LBM_OK) return rc;
+    }
+    return LBM_OK;
   }
+  if (n == 0) return LBM_OK;
+  int rc = ensure_side(h);
+  if (rc != LBM_OK) return rc;
+  const ColumnSet bulk{HALO, g.lx - 2 * HALO, 0};
+  const ColumnSet border{0, HALO, g.lx - HALO, HALO};
   LBM_HIP(h, hipEventRecord(h->ev_ready, h->stream));
   LBM_HIP(h, hipStreamWaitEvent(h->side, h->ev_ready, 0));
-  int rc = timed_on(h, LBM_PHASE_PBC, h->side, [&] { return launch_pbc(g, current(h), h->side); });
-  if (rc != LBM_OK) return rc;
-  LBM_HIP(h, hipEventRecord(h->ev_halo, h->side));
-  ColumnSet bulk{HALO, g.lx - 2 * HALO, 0};
-  rc = timed(h, LBM_PHASE_FUSED_BULK,
-             [&] { return launch_fused(g, current(h), other(h), h->cp, h->wp, h->stream, &bulk); });
-  if (rc != LBM_OK) return rc;
-  LBM_HIP(h, hipStreamWaitEvent(h->stream, h->ev_halo, 0));
-  ColumnSet border{0, HALO, g.lx - HALO, HALO};
-  rc = timed(h, LBM_PHASE_FUSED_BORDER,
-             [&] { return launch_fused(g, current(h), other(h), h->cp, h->wp, h->stream, &border); });
-  if (rc != LBM_OK) return rc;
-  h->cur ^= 1;
+  for (int32_t k = 0; k < n; ++k) {
+    if (k > 0) LBM_HIP(h, hipStreamWaitEvent(h->stream, h->ev_border, 0));
+    rc = timed_on(h, LBM_PHASE_PBC, h->side, [&] { return launch_pbc(g, current(h), h->side); });
+    if (rc != LBM_OK) return rc;
+    if (k > 0) LBM_HIP(h, hipStreamWaitEvent(h->side, h->ev_bulk, 0));
+    rc = timed_on(h, LBM_PHASE_FUSED_BORDER, h->side, [&] {
+      return launch_fused(g, current(h), other(h), h->cp, h->wp, h->side, &border);
+    });
+    if (rc != LBM_OK) return rc;
+    LBM_HIP(h, hipEventRecord(h->ev_border, h->side));
+    rc = timed(h, LBM_PHASE_FUSED_BULK,
+               [&] { return launch_fused(g, current(h), other(h), h->cp, h->wp, h->stream, &bulk); });
+    if (rc != LBM_OK) return rc;
+    LBM_HIP(h, hipEventRecord(h->ev_bulk, h->stream));
+    h->cur ^= 1;
+  }
+  LBM_HIP(h, hipStreamWaitEvent(h->stream, h->ev_border, 0));
   return LBM_OK;
 }
 
@@ -322,12 +355,8 @@ int lbm_step(lbm_handle* h, int32_t n) {
   if (!h->ready) return fail(h, LBM_ESTATE, "lattice not initialised");
   if (h->engine) return fail(h, LBM_ESTATE, "lattice is stepped by an engine (remove it first)");
   DeviceGuard dg(h->device);
+  if (h->cfg.path == LBM_PATH_REGIONS) return region_steps(h, n);
   for (int32_t i = 0; i < n; ++i) {
-    if (h->cfg.path == LBM_PATH_REGIONS) {
-      const int rc = region_step(h);
-      if (rc != LBM_OK) return rc;
-      continue;
-    }
     int rc;
     if (h->cfg.path == LBM_PATH_FUSED) {
       // one launch that wraps x; binary16-deviation lattices refresh the
@@ -362,11 +391,10 @@ int lbm_step_captured(lbm_handle* h, int32_t n) {
       cur_after = c.cur_after;
     }
   if (!exec) {
-    if (h->cfg.path == LBM_PATH_REGIONS && !h->side) {
+    if (h->cfg.path == LBM_PATH_REGIONS) {
       // create the side stream outside the capture
-      LBM_HIP(h, hipStreamCreate(&h->side));
-      LBM_HIP(h, hipEventCreateWithFlags(&h->ev_ready, hipEventDisableTiming));
-      LBM_HIP(h, hipEventCreateWithFlags(&h->ev_halo, hipEventDisableTiming));
+      const int rs = ensure_side(h);
+      if (rs != LBM_OK) return rs;
     }
     // capture on a private stream (the caller's may be the null stream,
     // which cannot be captured); the graph is launched on the caller's
@@ -637,7 +665,8 @@ void lbm_destroy(lbm_handle* h) {
       (void)hipStreamSynchronize(h->side);
       (void)hipStreamDestroy(h->side);
       (void)hipEventDestroy(h->ev_ready);
-      (void)hipEventDestroy(h->ev_halo);
+      (void)hipEventDestroy(h->ev_border);
+      (void)hipEventDestroy(h->ev_bulk);
     }
   }
   delete h;

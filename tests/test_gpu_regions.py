@@ -1,6 +1,6 @@
-"""Region-split step (bulk columns overlapped with pbc on a second stream,
-then the border columns): bit-identical to the fused step, and within the
-FP64 tolerance of the oracle."""
+"""Region-split step (bulk columns on the caller's stream, pbc and the border
+columns on a second stream, overlapped): bit-identical to the fused step,
+and within the FP64 tolerance of the oracle."""
 import numpy as np
 import pytest
 
@@ -27,6 +27,25 @@ def test_regions_equal_fused(lx, ly, storage, layout):
         with lattice(ns, path=path, storage=storage, layout=layout) as lat:
             lat.init_rt(rt)
             lat.step(9)
+            out.append(lat.get())
+    assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("storage", [lbm.LBM_FP64, lbm.LBM_FP32])
+@pytest.mark.parametrize("lx,ly", [(1024, 1024), (515, 700)])
+def test_regions_equal_fused_large(lx, ly, storage):
+    """Lattices where one bulk launch takes long enough that a border launch
+    on the other stream ordered wrongly against it would change the result;
+    several step calls, so the ordering across calls is exercised too."""
+    ns = inputs.rt_config(lx, ly)
+    rt = inputs.rt_perturbation(4, ly)
+    out = []
+    for path in (lbm.LBM_PATH_FUSED, lbm.LBM_PATH_REGIONS):
+        with lattice(ns, path=path, storage=storage) as lat:
+            lat.init_rt(rt)
+            lat.step(5)
+            lat.conservation()
+            lat.step(6)
             out.append(lat.get())
     assert np.array_equal(out[0], out[1])
 
