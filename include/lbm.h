@@ -254,7 +254,8 @@ int lbm_wall_factors(double t_wall, double out[LBM_NPOP]);
  * that chose pull over push.  Copies between two caller device buffers of
  * `bytes` bytes (a multiple of 16, both 16-byte aligned) on `stream`,
  * asynchronously:
- *   LBM_PROBE_COPY: dst[i] = src[i], 16 bytes per lane, all bytes;
+ *   LBM_PROBE_COPY: dst[i] = src[i], all bytes, in 16-byte vectors (four
+ *                   per lane per pass, non-temporal loads and stores);
  *   LBM_PROBE_MRAW: dst[64 + i] = src[64 + i + shift] (misaligned read);
  *   LBM_PROBE_ARMW: dst[64 + i + shift] = src[64 + i] (misaligned write);
  * for MRAW/ARMW elements are doubles, i < bytes / 8 - 128 and |shift| <= 64,

@@ -349,6 +349,22 @@ def test_bandwidth_probe_copies(mode, shift):
     assert np.all(d[untouched] == -1.0)
 
 
+@pytest.mark.parametrize("n16", [128, 3109, 1000003, 65536 * 1024 + 12345])
+def test_bandwidth_probe_copy_sizes(n16):
+    """The copy probe moves every 16-byte vector exactly once: sizes that
+    leave a partial pass, and one above the grid cap (several passes)."""
+    import torch
+    src = torch.randint(-2**62, 2**62, (2 * n16,), dtype=torch.int64, device="cuda")
+    dst = torch.zeros(2 * n16 + 2, dtype=torch.int64, device="cuda")
+    lbm.lbm_probe_bandwidth(0, src.data_ptr(), dst.data_ptr(), 16 * n16, 0,
+                            torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:2 * n16], src)
+    assert int(dst[2 * n16:].abs().sum()) == 0
+    del src, dst
+    torch.cuda.empty_cache()
+
+
 def test_bandwidth_probe_rejects_bad_arguments():
     import torch
     buf = torch.empty(4096, dtype=torch.uint8, device="cuda")
