@@ -211,10 +211,11 @@ def kernel_bandwidth(kernels: dict, sites: int, lx: int, ly: int, elem_bytes: in
     return kernels
 
 
-def cpu_baseline(seconds: float):
+def cpu_baseline(seconds: float, small_steps: int = 100):
     """The FP64 oracle, as it stands, stepping a 2048 x 256 strip of the
     Rayleigh-Taylor workload (same Lx and initial-state recipe, 256 rows)
-    for at least `seconds` of wall time."""
+    for at least `seconds` of wall time; beside it, the oracle's run of the
+    whole 64 x 128 workload (`small_steps` steps)."""
     import oracle
     from paper_1703_00185_amd import inputs
     lx, ly = 2048, 256
@@ -228,10 +229,20 @@ def cpu_baseline(seconds: float):
         el = time.perf_counter() - t0
         if el >= seconds:
             break
+    small = None
+    if small_steps > 0:
+        ns1 = inputs.rt_config(64, 128)
+        f1 = oracle.init_rt(64, 128, ns1, inputs.rt_perturbation(0, 128))
+        t1 = time.perf_counter()
+        f1 = oracle.run(f1, ns1, small_steps)
+        el1 = time.perf_counter() - t1
+        small = {"workload": "rayleigh_taylor_64x128_fp64", "steps": small_steps, "seconds": el1,
+                 "us_per_step": el1 / small_steps * 1e6, "mlups": 64 * 128 * small_steps / el1 / 1e6}
     return {"value": lx * ly * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"{steps} FP64 oracle steps of a {lx}x{ly} Rayleigh-Taylor strip (NumPy, "
                       f"single-threaded elementwise ops; {len(os.sched_getaffinity(0))} host cores "
-                      f"visible), {el:.1f} s"}
+                      f"visible), {el:.1f} s",
+            "small_lattice_64x128": small}
 
 
 def main() -> int:

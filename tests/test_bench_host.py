@@ -67,7 +67,8 @@ def test_measured_traffic_is_keyed_by_sources_and_lattice(tmp_path, monkeypatch)
 
 
 def test_cpu_baseline_reports_the_oracle():
-    out = bench.cpu_baseline(0.0)  # one oracle step of the 2048 x 256 strip
+    out = bench.cpu_baseline(0.0, small_steps=2)  # one step of the strip, 2 of 64 x 128
     assert out["kind"] == "oracle" and out["unit"] == "MLUPS" and out["cores"] == 1
     assert out["value"] > 0
     assert "2048x256" in out["sample"]
+    assert out["small_lattice_64x128"]["steps"] == 2 and out["small_lattice_64x128"]["mlups"] > 0
