@@ -144,6 +144,14 @@ int ensure_side(lbm_handle* h) {
   return LBM_OK;
 }
 
+// One step of the fused path: one launch that wraps x; binary16-deviation
+// lattices refresh the halo columns first and run the non-wrapping kernel.
+int fused_step(lbm_handle* h) {
+  int rc = h->geo.storage == STORAGE_F16DEV ? run_phase(h, LBM_PHASE_PBC) : LBM_OK;
+  if (rc == LBM_OK) rc = run_phase(h, LBM_PHASE_FUSED);
+  return rc;
+}
+
 // n steps of the region path.  Step k runs the fused kernel on the bulk
 // columns 3..Lx-4 (which pull from no halo) on the caller's stream, and pbc
 // followed by the 3 + 3 border columns on the side stream, concurrently.
@@ -164,7 +172,7 @@ int region_steps(lbm_handle* h, int32_t n) {
   const Geometry& g = h->geo;
   if (g.lx < 7) {
     for (int32_t k = 0; k < n; ++k) {
-      const int rc = run_phase(h, LBM_PHASE_FUSED);
+      const int rc = fused_step(h);
       if (rc != LBM_OK) return rc;
     }
     return LBM_OK;
@@ -359,10 +367,7 @@ int lbm_step(lbm_handle* h, int32_t n) {
   for (int32_t i = 0; i < n; ++i) {
     int rc;
     if (h->cfg.path == LBM_PATH_FUSED) {
-      // one launch that wraps x; binary16-deviation lattices refresh the
-      // halo columns first and run the non-wrapping kernel
-      rc = h->geo.storage == STORAGE_F16DEV ? run_phase(h, LBM_PHASE_PBC) : LBM_OK;
-      if (rc == LBM_OK) rc = run_phase(h, LBM_PHASE_FUSED);
+      rc = fused_step(h);
     } else {
       rc = run_phase(h, LBM_PHASE_PBC);
       if (rc == LBM_OK) rc = run_phase(h, LBM_PHASE_PROPAGATE);

@@ -17,9 +17,11 @@ def _gpu():
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-@pytest.mark.parametrize("storage", [lbm.LBM_FP64, lbm.LBM_FP32])
+@pytest.mark.parametrize("storage", [lbm.LBM_FP64, lbm.LBM_FP32, lbm.LBM_FP16DEV])
 @pytest.mark.parametrize("lx,ly", [(3, 6), (6, 12), (7, 20), (37, 70), (64, 128), (130, 257)])
 def test_regions_equal_fused(lx, ly, storage, layout):
+    """Every storage type, including lattices too narrow for a bulk region
+    (which take the fused step: pbc first for binary16 deviations)."""
     ns = inputs.rt_config(lx, ly)
     rt = inputs.rt_perturbation(2, ly)
     out = []
@@ -31,7 +33,7 @@ def test_regions_equal_fused(lx, ly, storage, layout):
     assert np.array_equal(out[0], out[1])
 
 
-@pytest.mark.parametrize("storage", [lbm.LBM_FP64, lbm.LBM_FP32])
+@pytest.mark.parametrize("storage", [lbm.LBM_FP64, lbm.LBM_FP32, lbm.LBM_FP16DEV])
 @pytest.mark.parametrize("lx,ly", [(1024, 1024), (515, 700)])
 def test_regions_equal_fused_large(lx, ly, storage):
     """Lattices where one bulk launch takes long enough that a border launch
