@@ -168,7 +168,8 @@ size_t lbm_required_bytes(const lbm_config *cfg);
 int lbm_create(const lbm_config *cfg, void *dev_mem, size_t dev_bytes,
                void *stream, lbm_handle **out);
 
-/* Rebind the handle to another stream (asynchronous calls go there). */
+/* Rebind the handle to another stream (asynchronous calls go there).
+ * Errors: EINVAL (NULL handle), ESTATE (the lattice is in an engine). */
 int lbm_set_stream(lbm_handle *h, void *stream);
 
 /* Set the Rayleigh-Taylor initial state (see lbm_rt_params); computed on
@@ -277,9 +278,9 @@ int lbm_probe_bandwidth(int32_t mode, const void *src, void *dst, size_t bytes, 
  * lbm_engine_required_bytes) holds the slot table only.
  *
  * While a lattice is in an engine, the engine steps it on the engine's
- * stream (the handle is rebound to that stream); lbm_step, lbm_run_phase,
- * lbm_init_rt, lbm_set_populations and lbm_set_reference on it fail with
- * ESTATE; reads (moments, conservation, populations, sites) first
+ * stream (the handle is rebound to that stream, and back to its own when it
+ * leaves the engine); lbm_set_stream, lbm_step, lbm_run_phase, lbm_init_rt,
+ * lbm_set_populations and lbm_set_reference on it fail with ESTATE; reads (moments, conservation, populations, sites) first
  * synchronise with the engine.  lbm_destroy of such a handle removes it
  * from its engine first.
  * ---------------------------------------------------------------------- */
@@ -308,7 +309,8 @@ int lbm_engine_create(int32_t max_slots, void *dev_mem, size_t dev_bytes, void *
 int lbm_engine_add(lbm_engine *e, lbm_handle *h, int32_t steps, int32_t *slot);
 
 /* Take the lattice of `slot` out of the engine (its state stays in its
- * handle, at the step it reached).  Synchronises the engine stream. */
+ * handle, at the step it reached) and rebind the handle to the stream it
+ * had when it was added.  Synchronises the engine stream. */
 int lbm_engine_remove(lbm_engine *e, int32_t slot);
 
 /* Enqueue n engine steps (asynchronous): each lattice with steps left

@@ -29,6 +29,7 @@ struct lbm_engine {
   std::vector<SlotDesc> slots;        // host copies, as uploaded
   std::vector<lbm_handle*> handles;   // nullptr: free slot
   std::vector<int> steps_left;        // last known (from status)
+  std::vector<int> status_init;       // (steps_left, cur) per slot as uploaded on add
   std::vector<int> table[2];
   int graph_classes = 0;              // storage types with a step node in the graph (bit mask)
   hipGraph_t graph = nullptr;
@@ -232,6 +233,7 @@ int lbm_engine_create(int32_t max_slots, void* dev_mem, size_t dev_bytes, void* 
   e->slots.assign(max_slots, SlotDesc{});
   e->handles.assign(max_slots, nullptr);
   e->steps_left.assign(max_slots, 0);
+  e->status_init.assign(2 * static_cast<size_t>(max_slots), 0);
   int cus = 0;
   DeviceGuard dg(e->device);
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, e->device) != hipSuccess || cus <= 0)
@@ -300,7 +302,8 @@ int lbm_engine_add(lbm_engine* e, lbm_handle* h, int32_t steps, int32_t* slot) {
   if (s == e->max_slots) return efail(e, LBM_ENOMEM, "no free slot");
   DeviceGuard dg(e->device);
   ENG_HIP(e, hipStreamSynchronize(h->stream));  // the lattice's own pending work
-  SlotDesc d{};
+  SlotDesc& d = e->slots[s];
+  d = SlotDesc{};
   d.buf[0] = h->buf[0];
   d.buf[1] = h->buf[1];
   d.pstride = h->geo.pstride;
@@ -313,20 +316,25 @@ int lbm_engine_add(lbm_engine* e, lbm_handle* h, int32_t steps, int32_t* slot) {
   d.steps_left = steps;
   d.cp = h->cp;
   d.wp = h->wp;
-  e->slots[s] = d;
   e->handles[s] = h;
   e->steps_left[s] = steps;
-  const int st[2] = {steps, h->cur};
+  // copies only from engine-owned host memory, which outlives them
+  e->status_init[2 * s] = steps;
+  e->status_init[2 * s + 1] = h->cur;
   ENG_HIP(e, hipMemcpyAsync(e->d_slots + s, &d, sizeof(SlotDesc), hipMemcpyHostToDevice, e->stream));
-  ENG_HIP(e, hipMemcpyAsync(e->d_status + 2 * s, st, sizeof(st), hipMemcpyHostToDevice, e->stream));
+  ENG_HIP(e, hipMemcpyAsync(e->d_status + 2 * s, &e->status_init[2 * s], 2 * sizeof(int),
+                            hipMemcpyHostToDevice, e->stream));
   const int rc = upload_table(e);
   if (rc != LBM_OK) {
     e->handles[s] = nullptr;
+    e->steps_left[s] = 0;
+    (void)hipStreamSynchronize(e->stream);
     return rc;
   }
   ENG_HIP(e, hipStreamSynchronize(e->stream));
   h->engine_slot = s;
   h->engine = e;
+  h->home_stream = h->stream;
   h->stream = e->stream;
   *slot = s;
   return LBM_OK;
@@ -341,6 +349,7 @@ int lbm_engine_remove(lbm_engine* e, int32_t slot) {
   lbm_handle* h = e->handles[slot];
   h->engine_slot = -1;
   h->engine = nullptr;
+  h->stream = h->home_stream;  // ordered: the engine stream is synchronised below
   e->handles[slot] = nullptr;
   e->steps_left[slot] = 0;
   e->slots[slot] = SlotDesc{};
@@ -451,10 +460,13 @@ void lbm_engine_destroy(lbm_engine* e) {
   {
     DeviceGuard dg(e->device);
     (void)read_status(e);
+    // read_status may have queued a table upload from e's host memory
+    (void)hipStreamSynchronize(e->stream);
     for (int s = 0; s < e->max_slots; ++s)
       if (e->handles[s]) {
         e->handles[s]->engine_slot = -1;
         e->handles[s]->engine = nullptr;
+        e->handles[s]->stream = e->handles[s]->home_stream;
       }
     drop_graph(e);
   }

@@ -19,6 +19,7 @@ struct lbm_handle {
   int cur = 0;  // buffer holding the current populations
   int engine_slot = -1;          // slot while an ensemble engine steps this lattice
   lbm_engine* engine = nullptr;  // that engine
+  hipStream_t home_stream = nullptr;  // the handle's stream before it joined the engine
   hipStream_t stream = nullptr;
   int device = 0;
   bool ready = false;

@@ -320,6 +320,7 @@ int lbm_create(const lbm_config* cfg, void* dev_mem, size_t dev_bytes, void* str
 
 int lbm_set_stream(lbm_handle* h, void* stream) {
   if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
+  if (h->engine) return fail(h, LBM_ESTATE, "lattice is stepped by an engine (remove it first)");
   h->stream = static_cast<hipStream_t>(stream);
   return LBM_OK;
 }

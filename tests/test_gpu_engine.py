@@ -124,6 +124,23 @@ def test_join_and_leave_mid_run():
     assert np.array_equal(got_c, _alone(c_spec, 2, 4))
 
 
+def test_member_keeps_the_engine_stream_until_it_leaves():
+    """An engine member cannot be rebound to another stream; once removed
+    it can again."""
+    lat, _ = _lattice(MIX[0], 0)
+    eng = lbm.Engine(max_slots=2)
+    try:
+        slot = eng.add(lat, 3)
+        with pytest.raises(lbm.LbmError) as ei:
+            lbm.lbm_set_stream(lat.h, lat.stream.cuda_stream)
+        assert ei.value.status == lbm.LBM_ESTATE
+        eng.remove(slot)
+        lbm.lbm_set_stream(lat.h, lat.stream.cuda_stream)
+    finally:
+        eng.close()
+        lat.close()
+
+
 def test_autotune_leaves_state_unchanged_and_picks_a_valid_tiling():
     lats = [_lattice(spec, i)[0] for i, spec in enumerate(MIX[:5])]
     eng = lbm.Engine(max_slots=8)
