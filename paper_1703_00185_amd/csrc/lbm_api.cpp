@@ -134,10 +134,13 @@ int timed(lbm_handle* h, int phase, F&& launch) {
 }
 
 // The second stream and events of the region path (created outside any
-// stream capture).
+// stream capture).  The stream is non-blocking: every ordering the region
+// schedule needs is an explicit event, and a blocking stream would also be
+// ordered against the legacy null stream, serialising the bulk launches
+// with the border launches when the caller steps on the null stream.
 int ensure_side(lbm_handle* h) {
   if (h->side) return LBM_OK;
-  LBM_HIP(h, hipStreamCreate(&h->side));
+  LBM_HIP(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
   LBM_HIP(h, hipEventCreateWithFlags(&h->ev_ready, hipEventDisableTiming));
   LBM_HIP(h, hipEventCreateWithFlags(&h->ev_border, hipEventDisableTiming));
   LBM_HIP(h, hipEventCreateWithFlags(&h->ev_bulk, hipEventDisableTiming));
