@@ -6,6 +6,13 @@
 * Total mass is conserved by the whole step, walls included.
 * After a step without gravity, the wall rows are at rest at the wall
   temperature (bc runs after propagate and before collide, Sec. 2).
+* With gravity, bc must come before collide: bc leaves each wall-row site
+  at rest with its density rho_s, and the collision then adds exactly
+  rho_s g to its momentum and lowers its temperature to T_wall - |g|^2 / D
+  (the balance laws of Sec. 2); collide followed by bc would leave it at
+  rest.
+* The global totals of an equilibrium state are the moments of the
+  Maxwellian summed over the sites.
 * The initial state is in hydrostatic balance: the closed form against
   numerical quadrature of d ln p / dy = r g_y / T (R4, R12).
 """
@@ -56,6 +63,61 @@ def test_wall_rows_at_rest_at_wall_temperature_after_step():
         assert np.max(np.abs(uy[:, rows])) < 1e-15
         assert np.max(np.abs(T[:, rows] - tw)) < 1e-14
     assert np.max(np.abs(uy[:, 3:21])) > 1e-4  # the bulk was not thermalised
+
+
+@pytest.mark.parametrize("gx,gy,tau", [(2e-4, -3e-4, 0.8), (0.0, -1e-3, 0.6), (-5e-4, 4e-4, 1.4)])
+def test_wall_rows_gain_rho_g_after_step_with_gravity(gx, gy, tau):
+    """Step order of Sec. 2: propagate, bc, collide.  bc leaves every
+    wall-row site at rest at the wall temperature with density rho_s; the
+    collision relaxes towards the equilibrium at u + tau g = tau g, so the
+    site leaves the step with momentum exactly rho_s g (mass unchanged) and
+    energy (1/2) sum |c|^2 f = rho_s T_wall, i.e. T = T_wall - |g|^2 / D.
+    If collide ran before bc the wall rows would end at rest."""
+    cfg = inputs.rt_config(9, 20, tau=tau, t_bottom=1.08, t_top=0.93)
+    cfg.gx, cfg.gy = gx, gy
+    rng = np.random.default_rng(21)
+    f = oracle.equilibrium(rng.uniform(0.8, 1.2, (9, 20)), rng.uniform(-.05, .05, (9, 20)),
+                           rng.uniform(-.05, .05, (9, 20)), rng.uniform(.92, 1.08, (9, 20)))
+    f = f * (1.0 + inputs.noise(22, f.shape, 0.01))
+    g = oracle.step(f, cfg)
+    k = oracle.constants()
+    rho = g.sum(axis=0)
+    jx = (k.cx[:, None, None] * g).sum(axis=0)
+    jy = (k.cy[:, None, None] * g).sum(axis=0)
+    _, _, _, T = oracle.moments(g)
+    g2 = gx * gx + gy * gy
+    for rows, tw in ((slice(0, 3), 1.08), (slice(17, 20), 0.93)):
+        assert np.max(np.abs(jx[:, rows] - rho[:, rows] * gx)) < 1e-15
+        assert np.max(np.abs(jy[:, rows] - rho[:, rows] * gy)) < 1e-15
+        assert np.max(np.abs(T[:, rows] - (tw - g2 / 2))) < 1e-14
+    # the bulk rows carry the momentum of the initial state, not rho g
+    assert np.max(np.abs(jy[:, 3:17] - rho[:, 3:17] * gy)) > 1e-3
+
+
+def test_totals_of_equilibrium_state_are_summed_maxwellian_moments():
+    """totals(): mass sum rho, momentum sum rho u, energy (1/2) sum |c|^2 f =
+    sum rho (|u|^2 + D T) / 2 at every site of an equilibrium state (the
+    equilibrium's moments through 2nd order are the Maxwellian's)."""
+    rng = np.random.default_rng(5)
+    shape = (7, 11)
+    rho = rng.uniform(0.7, 1.3, shape)
+    ux = rng.uniform(-0.08, 0.08, shape)
+    uy = rng.uniform(-0.08, 0.08, shape)
+    T = rng.uniform(0.9, 1.1, shape)
+    f = oracle.equilibrium(rho, ux, uy, T)
+    mass, jx, jy, energy = oracle.totals(f)
+    assert abs(mass - rho.sum()) < 1e-13
+    assert abs(jx - (rho * ux).sum()) < 1e-13
+    assert abs(jy - (rho * uy).sum()) < 1e-13
+    assert abs(energy - (0.5 * rho * (ux * ux + uy * uy + 2.0 * T)).sum()) < 1e-12
+    # and of a single displaced population: its own mass, r e_l and r^2 |e_l|^2 / 2
+    k = oracle.constants()
+    for l in (0, 7, 19, 36):
+        one = np.zeros((37, 3, 4))
+        one[l, 2, 1] = 0.25
+        m, px, py, e = oracle.totals(one)
+        assert (m, px, py) == (0.25, 0.25 * k.cx[l], 0.25 * k.cy[l])
+        assert abs(e - 0.125 * (k.cx[l] ** 2 + k.cy[l] ** 2)) < 1e-16
 
 
 def test_step_sites_matches_full_step():
