@@ -14,10 +14,8 @@ from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_int32, c_int64, 
 
 import numpy as np
 
-# The in-tree build; PAPER_1703_00185_AMD_LIB may name another build of the
-# same sources (used to compare tuning variants side by side).
-LIB_PATH = os.environ.get("PAPER_1703_00185_AMD_LIB") or os.path.join(
-    os.path.dirname(os.path.abspath(__file__)), "libd2q37.so")
+# The in-tree build of the library (paper_1703_00185_amd/build.py).
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libd2q37.so")
 
 NPOP = 37
 MAX_MODES = 32
