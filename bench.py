@@ -7,11 +7,14 @@ step, periodic x by wrapping the source column).  A step is one update of
 the whole lattice.  Inputs are resident in HBM before the timed region.
 Beside it, for comparison: the same step in the planar layout, the
 separate path (pbc, propagate, bc, collide), FP32 and FP16-deviation
-storage, the region split, the 64 x 128 workload (plain and graph-replayed
-launches), copy probes of the attainable bandwidth, and a bounded sample
-of the serving workload (Poisson arrivals of uneven FP64/FP32 requests
-stepped together by the ensemble engine) for the p50/p99 completion
-latency against a one-request-at-a-time FP64 server.
+storage with their field errors against the FP64 path after the same
+steps, the region split, the 64 x 128 workload (plain and graph-replayed
+launches), copy probes of the attainable bandwidth, the batched ensemble
+(256 uneven FP32 lattices stepped by the autotuned engine, against the same
+lattices one at a time), and a bounded sample of the serving workload
+(Poisson arrivals of uneven FP64/FP32 requests stepped together by the
+ensemble engine) for the p50/p99 completion latency against a
+one-request-at-a-time FP64 server.
 
 Prints one JSON line: MLUPS of the fused path as `value`, the roofline of
 the dominant kernel (the fused kernel: 592 algorithmic bytes per site per
@@ -71,7 +74,7 @@ def measured_traffic(lx: int, ly: int, layout: str):
 
 
 def time_path(lbm, ns, rt, path: int, steps: int, warmup: int, extra: dict,
-              breakdown_steps: int = 0, graph_chunk: int = 0):
+              breakdown_steps: int = 0, graph_chunk: int = 0, fields: bool = False):
     """Time `steps` steps of one path.  The timed region holds only the
     step launches: no per-launch markers (they add a few microseconds per
     launch, and cross-stream ones more); two HIP events on the lattice's
@@ -80,7 +83,8 @@ def time_path(lbm, ns, rt, path: int, steps: int, warmup: int, extra: dict,
     launches included).  With `breakdown_steps`, a separate run with a HIP
     event pair around every launch gives the per-kernel breakdown; with
     `graph_chunk`, the same steps are also replayed from a captured graph
-    of that many steps."""
+    of that many steps.  With `fields`, the per-site moments (rho, ux, uy,
+    T) after the warmup and timed steps are returned as well."""
     import torch
     cfg = lbm.config_from(ns, path=path, **extra)
     lat = lbm.Lattice(cfg)
@@ -97,6 +101,7 @@ def time_path(lbm, ns, rt, path: int, steps: int, warmup: int, extra: dict,
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         span_ms = ev0.elapsed_time(ev1)
+        moments = lat.moments() if fields else None
         kernels = {}
         if breakdown_steps:
             lbm.lbm_set_timing(lat.h, True)
@@ -123,7 +128,31 @@ def time_path(lbm, ns, rt, path: int, steps: int, warmup: int, extra: dict,
     finally:
         lat.close()
     return {"wall": wall, "span_ms": span_ms, "kernels": kernels, "cons": cons, "layout": layout,
-            "graph_s_per_step": graph_wall}
+            "graph_s_per_step": graph_wall, "moments": moments}
+
+
+def field_errors(ref, got) -> dict:
+    """Largest differences of the density (relative), temperature and
+    velocity fields of `got` from `ref` (each a tuple rho, ux, uy, T)."""
+    import numpy as np
+    rho0, ux0, uy0, T0 = ref
+    rho, ux, uy, T = got
+    return {"rho_max_rel": float(np.max(np.abs(rho - rho0) / rho0)),
+            "T_max_abs": float(np.max(np.abs(T - T0))),
+            "u_max_abs": float(np.max(np.hypot(ux - ux0, uy - uy0))),
+            "u_scale": float(np.max(np.hypot(ux0, uy0)))}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def single_kernel(name: str, run: dict, steps: int) -> dict:
@@ -239,6 +268,7 @@ def cpu_baseline(seconds: float, small_steps: int = 100):
         small = {"workload": "rayleigh_taylor_64x128_fp64", "steps": small_steps, "seconds": el1,
                  "us_per_step": el1 / small_steps * 1e6, "mlups": 64 * 128 * small_steps / el1 / 1e6}
     return {"value": lx * ly * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{steps} FP64 oracle steps of a {lx}x{ly} Rayleigh-Taylor strip (NumPy, "
                       f"single-threaded elementwise ops; {len(os.sched_getaffinity(0))} host cores "
                       f"visible), {el:.1f} s",
@@ -264,6 +294,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests of the bounded serving sample (p50/p99 latency); 0 skips it")
+    ap.add_argument("--ensemble-lattices", type=int, default=256,
+                    help="lattices of the batched-ensemble leg (FP32, autotuned engine); 0 skips it")
+    ap.add_argument("--ensemble-steps", type=int, default=51,
+                    help="engine steps of the ensemble leg (the first builds the graph, untimed)")
     ap.add_argument("--copy-gib", type=float, default=2.0,
                     help="size of the plain-copy reference (read GiB = write GiB)")
     args = ap.parse_args()
@@ -296,8 +330,9 @@ def main() -> int:
         log(f"copy probe of {args.copy_gib} GiB: {copy['copy']['gbs']:.0f} GB/s; "
             f"mraw(+1) {copy['mraw']['1']:.0f}, armw(+1) {copy['armw']['1']:.0f} GB/s")
     log(f"fused path {lx}x{ly}: {args.warmup} warmup + {args.steps} timed steps")
-    run = time_path(lbm, ns, rt, lbm.LBM_PATH_FUSED, args.steps, args.warmup, extra)
+    run = time_path(lbm, ns, rt, lbm.LBM_PATH_FUSED, args.steps, args.warmup, extra, fields=True)
     wall, cons, layout = run["wall"], run["cons"], run["layout"]
+    fp64_fields = run.pop("moments")
     kern = kernel_bandwidth(single_kernel("fused", run, args.steps), sites, lx, ly)
     mlups = sites * args.steps / wall / 1e6
     log(f"fused: {mlups:.1f} MLUPS, {wall / args.steps * 1e3:.3f} ms/step, "
@@ -336,15 +371,21 @@ def main() -> int:
         # binary16 deviations launch pbc before the fused kernel: per-launch breakdown
         r3 = time_path(lbm, ns, rt, lbm.LBM_PATH_FUSED, args.steps, args.warmup,
                        dict(extra, storage=storage),
-                       breakdown_steps=breakdown if storage == lbm.LBM_FP16DEV else 0)
+                       breakdown_steps=breakdown if storage == lbm.LBM_FP16DEV else 0, fields=True)
+        errors = field_errors(fp64_fields, r3.pop("moments"))
         w3 = r3["wall"]
         k3 = r3["kernels"] if storage == lbm.LBM_FP16DEV else single_kernel("fused", r3, args.steps)
         k3 = kernel_bandwidth(k3, sites, lx, ly, elem_bytes=eb)
         reduced[name] = {"mlups": sites * args.steps / w3 / 1e6, "ms_per_step": w3 / args.steps * 1e3,
                          "speedup_vs_fp64": wall / w3, "bytes_per_site": 2 * 37 * eb,
-                         "kernels": k3}
+                         "kernels": k3,
+                         "error_vs_fp64": dict(errors, steps=args.warmup + args.steps,
+                                               reference="FP64 GPU path, same steps")}
         log(f"{name} storage: {reduced[name]['mlups']:.1f} MLUPS, "
-            f"fused kernel {k3['fused']['gbs']:.0f} GB/s")
+            f"fused kernel {k3['fused']['gbs']:.0f} GB/s; after {args.warmup + args.steps} steps "
+            f"max |drho|/rho {errors['rho_max_rel']:.1e}, |dT| {errors['T_max_abs']:.1e}, "
+            f"|du| {errors['u_max_abs']:.1e} (max |u| {errors['u_scale']:.1e})")
+    del fp64_fields
 
     log(f"region path {lx}x{ly}: {args.warmup} warmup + {args.steps} timed steps")
     r4 = time_path(lbm, ns, rt, lbm.LBM_PATH_REGIONS, args.steps, args.warmup, extra,
@@ -360,6 +401,16 @@ def main() -> int:
     log("64x128 workload, 100 steps: plain and graph-captured launches")
     small = small_lattice(lbm, inputs)
     log("64x128: " + ", ".join(f"{k} {v['us_per_step']:.1f} us/step" for k, v in small.items()))
+
+    ensemble = None
+    if args.ensemble_lattices > 0:
+        from paper_1703_00185_amd.ensemble_bench import run_ensemble
+        torch.cuda.empty_cache()
+        log(f"batched ensemble: {args.ensemble_lattices} FP32 lattices, autotuned engine, "
+            f"{args.ensemble_steps} steps")
+        ensemble = run_ensemble(lbm, inputs, lattices=args.ensemble_lattices,
+                                steps=args.ensemble_steps, sequential_steps=10, log=log)
+        torch.cuda.empty_cache()
 
     serving = None
     if args.serve_requests > 0:
@@ -397,7 +448,7 @@ def main() -> int:
                        "pstride": layout[2], "cstride": layout[3], "block": layout[5]}},
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kern, "separate": separate,
         "bandwidth_probe": copy, "reduced_storage": reduced, "regions": regions,
-        "other_layout": other_layout, "ensemble_serving": serving,
+        "other_layout": other_layout, "batched_ensemble": ensemble, "ensemble_serving": serving,
         "small_lattice_64x128": small,
         "paper_equivalent_gflops": 6472 * sites * args.steps / wall / 1e9,
     }

@@ -30,6 +30,72 @@ def draw_ensemble(seed: int, n: int):
             enumerate(zip(lx, ly, contrast))]
 
 
+def run_ensemble(lbm, inputs, lattices: int = 256, steps: int = 500, seed: int = 0,
+                 storage_name: str = "fp32", tune_reps: int = 2, sequential_steps: int = 50,
+                 log=None) -> dict:
+    """Build the ensemble on the current GPU, autotune the engine, time
+    `steps` engine steps (the first, which builds the step graph, is not
+    timed) and `sequential_steps` steps of each lattice alone; returns the
+    result record (the JSON object main() prints)."""
+    import torch
+    log = log or (lambda msg: print(msg, file=sys.stderr, flush=True))
+    storage = lbm.LBM_FP32 if storage_name == "fp32" else lbm.LBM_FP64
+    specs = draw_ensemble(seed, lattices)
+    lats = []
+    t0 = time.perf_counter()
+    for lx, ly, contrast, pseed in specs:
+        ns = inputs.rt_config(lx, ly, t_bottom=1 + contrast / 2, t_top=1 - contrast / 2)
+        lat = lbm.Lattice(lbm.config_from(ns, storage=storage))
+        lat.init_rt(inputs.rt_perturbation(pseed, ly))
+        lats.append(lat)
+    torch.cuda.synchronize()
+    sites = sum(lx * ly for lx, ly, _, _ in specs)
+    mem = sum(lat.nbytes for lat in lats)
+    log(f"[ensemble] {len(lats)} lattices, {sites / 1e6:.1f} M sites, {mem / 2**30:.1f} GiB, "
+        f"set up in {time.perf_counter() - t0:.1f} s")
+    try:
+        eng = lbm.Engine(max_slots=len(lats))
+        for lat in lats:
+            eng.add(lat, steps)
+        (block, groups, sched), tuned_ms = eng.tune(reps=tune_reps)
+        log(f"[ensemble] tuned: block {block}, groups {groups}, schedule {sched}, "
+            f"{tuned_ms:.3f} ms per step")
+        eng.step(1)  # graph build + warm-up (every lattice then runs steps - 1 more)
+        eng.status()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eng.step(steps - 1)
+        left = eng.status()
+        wall = time.perf_counter() - t0
+        assert int(left.max()) == 0
+        mlups = sites * (steps - 1) / wall / 1e6
+        log(f"[ensemble] engine: {mlups:.0f} MLUPS, {wall / (steps - 1) * 1e3:.3f} ms per step")
+        eng.close()
+
+        # one lattice at a time, same lattices, fused path, synchronised per lattice
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for lat in lats:
+            lat.step(sequential_steps)
+            torch.cuda.synchronize()
+        seq_wall = time.perf_counter() - t0
+        seq_mlups = sites * sequential_steps / seq_wall / 1e6
+        log(f"[ensemble] one at a time: {seq_mlups:.0f} MLUPS")
+    finally:
+        for lat in lats:
+            lat.close()
+    return {
+        "workload": f"{len(specs)} Rayleigh-Taylor lattices, Lx in 64..1024, Ly = 2 or 4 Lx, "
+                    f"{storage_name}, {steps} engine steps",
+        "lattices": len(specs), "sites": sites, "device_bytes": mem, "engine_mlups": mlups,
+        "engine_steps_timed": steps - 1, "engine_ms_per_step": wall / (steps - 1) * 1e3,
+        "tiling": {"block": block, "groups": groups, "schedule": ["chunked", "strided"][sched],
+                   "tuned_ms_per_step": tuned_ms},
+        "one_at_a_time_mlups": seq_mlups, "one_at_a_time_steps": sequential_steps,
+        "speedup": mlups / seq_mlups,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--lattices", type=int, default=256)
@@ -47,62 +113,9 @@ def main() -> int:
         return 1
     from paper_1703_00185_amd import inputs, lbm
 
-    storage = lbm.LBM_FP32 if args.storage == "fp32" else lbm.LBM_FP64
-    specs = draw_ensemble(args.seed, args.lattices)
-    lats = []
-    t0 = time.perf_counter()
-    for lx, ly, contrast, pseed in specs:
-        ns = inputs.rt_config(lx, ly, t_bottom=1 + contrast / 2, t_top=1 - contrast / 2)
-        lat = lbm.Lattice(lbm.config_from(ns, storage=storage))
-        lat.init_rt(inputs.rt_perturbation(pseed, ly))
-        lats.append(lat)
-    torch.cuda.synchronize()
-    sites = sum(lx * ly for lx, ly, _, _ in specs)
-    mem = sum(lat.nbytes for lat in lats)
-    print(f"[ensemble] {len(lats)} lattices, {sites / 1e6:.1f} M sites, {mem / 2**30:.1f} GiB, "
-          f"set up in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-
-    eng = lbm.Engine(max_slots=len(lats))
-    for lat in lats:
-        eng.add(lat, args.steps)
-    (block, groups, sched), tuned_ms = eng.tune(reps=args.tune_reps)
-    print(f"[ensemble] tuned: block {block}, groups {groups}, schedule {sched}, "
-          f"{tuned_ms:.3f} ms per step", file=sys.stderr, flush=True)
-    eng.step(1)  # graph build + warm-up (counted: every lattice then runs steps - 1 more)
-    eng.status()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    eng.step(args.steps - 1)
-    left = eng.status()
-    wall = time.perf_counter() - t0
-    assert int(left.max()) == 0
-    mlups = sites * (args.steps - 1) / wall / 1e6
-    print(f"[ensemble] engine: {mlups:.0f} MLUPS, {wall / (args.steps - 1) * 1e3:.3f} ms per step",
-          file=sys.stderr, flush=True)
-    eng.close()
-
-    # one lattice at a time, same lattices, fused path, synchronised per lattice
-    n_seq = args.sequential_steps
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for lat in lats:
-        lat.step(n_seq)
-        torch.cuda.synchronize()
-    seq_wall = time.perf_counter() - t0
-    seq_mlups = sites * n_seq / seq_wall / 1e6
-    print(f"[ensemble] one at a time: {seq_mlups:.0f} MLUPS", file=sys.stderr, flush=True)
-    for lat in lats:
-        lat.close()
-
-    print(json.dumps({
-        "workload": f"{len(specs)} Rayleigh-Taylor lattices, Lx in 64..1024, Ly = 2 or 4 Lx, "
-                    f"{args.storage}, {args.steps} steps",
-        "sites": sites, "device_bytes": mem, "engine_mlups": mlups,
-        "engine_ms_per_step": wall / (args.steps - 1) * 1e3,
-        "tiling": {"block": block, "groups": groups, "schedule": ["chunked", "strided"][sched],
-                   "tuned_ms_per_step": tuned_ms},
-        "one_at_a_time_mlups": seq_mlups, "speedup": mlups / seq_mlups,
-    }), flush=True)
+    out = run_ensemble(lbm, inputs, args.lattices, args.steps, args.seed, args.storage,
+                       args.tune_reps, args.sequential_steps)
+    print(json.dumps(out), flush=True)
     return 0
 
 

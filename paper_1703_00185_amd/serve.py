@@ -67,6 +67,7 @@ class Server:
         self.keep = set(keep)       # request ids whose final populations are kept
         self.kept = {}
         self.used = 0
+        self.events = []            # (time, "admit" | "retire", request id, slot)
 
     def config(self, r: Request):
         ns = self.inputs.rt_config(r.lx, r.ly)
@@ -102,6 +103,7 @@ class Server:
                 lat = lbm.Lattice(cfg)
                 lat.init_rt(self.inputs.rt_perturbation(r.seed, r.ly))
                 slot = self.engine.add(lat, r.steps)
+                self.events.append((time.perf_counter() - t0, "admit", r.rid, slot))
                 active[slot] = (r, lat, need)
                 left_of[slot] = r.steps
                 self.used += need
@@ -124,6 +126,7 @@ class Server:
                 if r.rid in self.keep:
                     self.kept[r.rid] = lat.get()
                 self.engine.remove(slot)
+                self.events.append((now, "retire", r.rid, slot))
                 lat.close()
                 self.used -= need
         makespan = time.perf_counter() - t0

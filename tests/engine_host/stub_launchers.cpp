@@ -1,0 +1,179 @@
+// Kernel launchers of the library (kernels.hpp, engine.hpp) for the CPU
+// stand-in of the HIP runtime: each launch is queued on its stream and, when
+// the stream runs it, touches the memory the real kernel would read and
+// write (first and last element of each lattice copy it uses, every element
+// of staging buffers), so that a launch that runs after its memory was freed
+// is reported by the sanitizer.  The engine's advance kernel is simulated
+// exactly (it is the state the host reads back).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "engine.hpp"
+#include "kernels.hpp"
+
+namespace d2q37 {
+namespace {
+
+size_t elem(int storage) { return storage == STORAGE_F64 ? 8 : storage == STORAGE_F32 ? 4 : 2; }
+
+// Last element of a lattice copy: (l, X, y) = (36, lx + 5, ly - 1).
+size_t last_byte(long long pstride, long long cstride, int lx, int ly, int storage) {
+  const long long idx = 36 * pstride + static_cast<long long>(lx + 5) * cstride + (ly - 1);
+  return static_cast<size_t>(idx) * elem(storage);
+}
+
+volatile unsigned char g_sink;
+
+void touch_read(const void* p, size_t last) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  g_sink = b[0];
+  g_sink = b[last];
+}
+void touch_write(void* p, size_t last) {
+  unsigned char* b = static_cast<unsigned char*>(p);
+  b[0] = 0;
+  b[last] = 0;
+}
+
+void enqueue(hipStream_t s, std::function<void()> op) { hipstub::of(s).ops.push_back(std::move(op)); }
+
+size_t last_of(const Geometry& g) { return last_byte(g.pstride, g.cstride, g.lx, g.ly, g.storage); }
+
+// Engine kernels.  The step kernel touches both copies of every active
+// slot with steps left; the advance kernel flips and counts as on the GPU.
+void engine_step_sim(const std::vector<std::vector<unsigned char>>& a) {
+  const SlotDesc* slots;
+  const int* table;
+  int m;
+  std::memcpy(&slots, a[0].data(), sizeof slots);
+  std::memcpy(&table, a[1].data(), sizeof table);
+  std::memcpy(&m, a[2].data(), sizeof m);
+  const int n = table[0];
+  for (int k = 0; k < n; ++k) {
+    const SlotDesc& d = slots[table[2 + k]];
+    if (d.steps_left <= 0) continue;
+    const size_t last = last_byte(d.pstride, d.cstride, d.lx, d.ly, d.storage);
+    touch_read(d.buf[d.cur], last);
+    touch_write(d.buf[d.cur ^ 1], last);
+  }
+}
+void engine_advance_sim(const std::vector<std::vector<unsigned char>>& a) {
+  SlotDesc* slots;
+  int m;
+  int* status;
+  std::memcpy(&slots, a[0].data(), sizeof slots);
+  std::memcpy(&m, a[1].data(), sizeof m);
+  std::memcpy(&status, a[2].data(), sizeof status);
+  for (int s = 0; s < m; ++s) {
+    SlotDesc& d = slots[s];
+    if (d.steps_left > 0) {
+      d.cur ^= 1;
+      d.steps_left -= 1;
+    }
+    status[2 * s] = d.steps_left;
+    status[2 * s + 1] = d.cur;
+  }
+}
+char g_step_f64, g_step_f32, g_advance;  // stand-in kernel "functions"
+
+struct Register {
+  Register() {
+    for (const void* f : {static_cast<const void*>(&g_step_f64), static_cast<const void*>(&g_step_f32)}) {
+      hipstub::sims().push_back({f, engine_step_sim});
+      hipstub::arg_sizes().push_back({f, {sizeof(void*), sizeof(void*), sizeof(int)}});
+    }
+    hipstub::sims().push_back({&g_advance, engine_advance_sim});
+    hipstub::arg_sizes().push_back({&g_advance, {sizeof(void*), sizeof(int), sizeof(void*)}});
+  }
+} g_register;
+
+}  // namespace
+
+hipError_t launch_pbc(const Geometry& g, void* f, hipStream_t s) {
+  const size_t last = last_of(g);
+  enqueue(s, [=] { touch_write(f, last); });
+  return hipSuccess;
+}
+hipError_t launch_propagate(const Geometry& g, const void* src, void* dst, hipStream_t s) {
+  const size_t last = last_of(g);
+  enqueue(s, [=] { touch_read(src, last); touch_write(dst, last); });
+  return hipSuccess;
+}
+hipError_t launch_bc(const Geometry& g, void* f, const WallParams&, hipStream_t s) { return launch_pbc(g, f, s); }
+hipError_t launch_collide(const Geometry& g, const void* src, void* dst, const CollideParams&, hipStream_t s) {
+  return launch_propagate(g, src, dst, s);
+}
+hipError_t launch_fused(const Geometry& g, const void* src, void* dst, const CollideParams&, const WallParams&,
+                        hipStream_t s, const ColumnSet*, bool) {
+  return launch_propagate(g, src, dst, s);
+}
+hipError_t launch_moments(const Geometry& g, const void* f, double* out, hipStream_t s) {
+  const size_t last = last_of(g);
+  const size_t n = 4 * static_cast<size_t>(g.lx) * g.ly;
+  enqueue(s, [=] { touch_read(f, last); for (size_t i = 0; i < n; ++i) out[i] = 1.0; });
+  return hipSuccess;
+}
+hipError_t launch_conservation(const Geometry& g, const void* f, double* partials, double* result, hipStream_t s) {
+  const size_t last = last_of(g);
+  enqueue(s, [=] {
+    touch_read(f, last);
+    for (int i = 0; i < CONS_BLOCKS * CONS_FIELDS; ++i) partials[i] = 0.0;
+    for (int k = 0; k < CONS_FIELDS; ++k) result[k] = 0.0;
+  });
+  return hipSuccess;
+}
+hipError_t launch_get_sites(const Geometry& g, const void* f, const int* xy, int n, double* out, hipStream_t s) {
+  const size_t last = last_of(g);
+  enqueue(s, [=] {
+    touch_read(f, last);
+    for (int i = 0; i < n; ++i)
+      for (int l = 0; l < 37; ++l) out[static_cast<size_t>(l) * n + i] = xy[2 * i] + xy[2 * i + 1];
+  });
+  return hipSuccess;
+}
+hipError_t launch_init_rt(const Geometry& g, void* f, const RtParams&, hipStream_t s) { return launch_pbc(g, f, s); }
+hipError_t launch_rt_reference(const Geometry& g, double* ref, double* inv_ref, const RtParams&, hipStream_t s) {
+  const int ly = g.ly;
+  enqueue(s, [=] { for (int y = 0; y < ly; ++y) { ref[y] = 1.0; inv_ref[y] = 1.0; } });
+  return hipSuccess;
+}
+hipError_t launch_encode_population(const Geometry& g, const double* in, void* f, int, hipStream_t s) {
+  const size_t last = last_of(g);
+  const size_t n = static_cast<size_t>(g.lx) * g.ly;
+  enqueue(s, [=] { double acc = 0; for (size_t i = 0; i < n; ++i) acc += in[i]; g_sink = acc > 0; touch_write(f, last); });
+  return hipSuccess;
+}
+hipError_t launch_decode_population(const Geometry& g, const void* f, double* out, int l, hipStream_t s) {
+  const size_t last = last_of(g);
+  const size_t n = static_cast<size_t>(g.lx) * g.ly;
+  enqueue(s, [=] { touch_read(f, last); for (size_t i = 0; i < n; ++i) out[i] = l; });
+  return hipSuccess;
+}
+hipError_t launch_probe(int, const void*, void*, size_t, int, hipStream_t) { return hipSuccess; }
+
+hipError_t launch_engine_step(int storage, const SlotDesc* slots, const int* table, int max_slots, int, int, int,
+                              hipStream_t s) {
+  const void* f = storage == STORAGE_F32 ? &g_step_f32 : &g_step_f64;
+  void* args[] = {&slots, &table, &max_slots};
+  return hipLaunchKernel(f, dim3(1), dim3(64), args, 0, s);
+}
+hipError_t launch_engine_advance(SlotDesc* slots, int max_slots, int* status, hipStream_t s) {
+  void* args[] = {&slots, &max_slots, &status};
+  return hipLaunchKernel(&g_advance, dim3(1), dim3(64), args, 0, s);
+}
+hipError_t engine_step_node(int storage, int block, int groups, int, void** func, dim3* grid, dim3* threads) {
+  if (groups <= 0) return hipErrorInvalidValue;
+  *func = storage == STORAGE_F32 ? static_cast<void*>(&g_step_f32) : static_cast<void*>(&g_step_f64);
+  *grid = dim3(groups);
+  *threads = dim3(block);
+  return hipSuccess;
+}
+hipError_t engine_advance_node(int, void** func, dim3* grid, dim3* threads) {
+  *func = &g_advance;
+  *grid = dim3(1);
+  *threads = dim3(256);
+  return hipSuccess;
+}
+
+}  // namespace d2q37

@@ -1,0 +1,77 @@
+"""The ensemble engine's host code under AddressSanitizer and
+UndefinedBehaviorSanitizer, on a CPU stand-in of the HIP runtime (no GPU).
+
+`tests/engine_host/hip/hip_runtime.h` replaces the HIP runtime API with host
+code in which every asynchronous copy, kernel launch and graph launch is
+queued on its stream and runs only at the synchronisation that covers it;
+`stub_launchers.cpp` stands in for the kernels (touching the memory each
+would read and write, and simulating the engine's advance kernel exactly).
+`join_leave.cpp` drives lbm_api.cpp and engine_api.cpp, unchanged, through
+the C ABI with the call sequences of the GPU engine tests: mixes under
+several tilings, lattices joining and leaving mid-run with slot reuse, read
+back of members and former members, serving-like churn, and a lattice
+destroyed while in an engine.  Any copy source, destination or lattice
+buffer that dies before the work using it has run is a sanitizer report.
+
+A second build plants one such mistake (the engine's add returns before
+the copies from its stack have run) and must be reported, so that the
+harness is known to catch this class of error.
+"""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1703_00185_amd", "csrc")
+HARNESS = os.path.join(ROOT, "tests", "engine_host")
+FLAGS = ["-std=c++17", "-g", "-O1", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+         "-fno-sanitize-recover=undefined"]
+ENV = dict(os.environ, ASAN_OPTIONS="detect_stack_use_after_return=1:detect_leaks=0")
+
+
+def _build(tmp_path, engine_src, name):
+    exe = str(tmp_path / name)
+    cmd = ["g++", *FLAGS, "-I", HARNESS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           "-x", "c++", os.path.join(CSRC, "lbm_api.cpp"), engine_src,
+           os.path.join(HARNESS, "stub_launchers.cpp"), os.path.join(HARNESS, "join_leave.cpp"),
+           "-o", exe]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr[-4000:]
+    return exe
+
+
+@pytest.fixture(scope="module")
+def gxx():
+    if not shutil.which("g++"):
+        pytest.skip("g++ not found")
+
+
+@pytest.mark.timeout(600)
+def test_engine_host_sequences_clean(tmp_path, gxx):
+    exe = _build(tmp_path, os.path.join(CSRC, "engine_api.cpp"), "join_leave")
+    res = subprocess.run([exe], capture_output=True, text=True, env=ENV, timeout=300)
+    assert res.returncode == 0, (res.stdout + res.stderr)[-6000:]
+    assert "engine host sequences: ok" in res.stdout
+
+
+@pytest.mark.timeout(600)
+def test_harness_reports_a_copy_outliving_its_source(tmp_path, gxx):
+    with open(os.path.join(CSRC, "engine_api.cpp")) as fh:
+        src = fh.read()
+    # plant: the engine's add copies (steps_left, cur) from a stack array and
+    # returns without waiting for its stream
+    planted, n1 = re.subn(r"ENG_HIP\(e, hipMemcpyAsync\(e->d_status \+ 2 \* s, &e->status_init\[2 \* s\],",
+                          "const int st_[2] = {steps, h->cur};\n  ENG_HIP(e, hipMemcpyAsync(e->d_status + 2 * s, st_,",
+                          src)
+    planted, n2 = re.subn(r"  ENG_HIP\(e, hipStreamSynchronize\(e->stream\)\);\n  h->engine_slot = s;",
+                          "  h->engine_slot = s;", planted)
+    assert n1 == 1 and n2 == 1, "the planted edit no longer applies to engine_api.cpp"
+    path = tmp_path / "engine_api_planted.cpp"
+    path.write_text(planted)
+    exe = _build(tmp_path, str(path), "join_leave_planted")
+    res = subprocess.run([exe], capture_output=True, text=True, env=ENV, timeout=300)
+    assert res.returncode != 0
+    assert "stack-use-after-return" in res.stderr
