@@ -26,7 +26,9 @@
  *     throws.  lbm_last_error() gives the reason of the last failure.
  *   - Device memory is owned by the caller: one block of at least
  *     lbm_required_bytes() bytes, 256-byte aligned, that must outlive the
- *     handle.  The library never allocates or frees device memory.
+ *     handle.  The library never allocates or frees device memory (its
+ *     one static array, the staging of lbm_get_sites_noalloc, is part of
+ *     its code object).
  *   - The HIP stream is owned by the caller.  Calls documented as
  *     asynchronous only enqueue work on it; calls that take or fill host
  *     arrays synchronise it before returning.
@@ -221,6 +223,20 @@ int lbm_set_populations(lbm_handle *h, const double *host);
  * on the host: EINVAL otherwise).  n may be at most lbm_layout()[4] / 304.
  * Uses the idle lattice copy as scratch.  Synchronises the stream. */
 int lbm_get_sites(lbm_handle *h, int32_t n, const int32_t *xs, const int32_t *ys, double *out);
+
+/* For callers that cannot allocate device memory or use the lattice's idle
+ * copy (code that must not call hipMalloc, tight serving loops): the same
+ * gather as lbm_get_sites, same arguments and results bit for bit, with
+ * its device staging (the gathered populations and the coordinates) in a
+ * fixed array of the library, one per GPU, held from the first call on that
+ * GPU until the process ends: LBM_NOALLOC_MAX_SITES * 304 bytes (2.4 MiB).
+ * Calls no allocating routine; the idle lattice copy is not touched.
+ * n may be at most LBM_NOALLOC_MAX_SITES (EINVAL otherwise).  Every call on
+ * one GPU shares that array: calls that overlap on one GPU (other threads,
+ * other streams) race and must be serialised by the caller.  Nothing in the
+ * array needs to start cleared.  Synchronises the stream. */
+#define LBM_NOALLOC_MAX_SITES 8192
+int lbm_get_sites_noalloc(lbm_handle *h, int32_t n, const int32_t *xs, const int32_t *ys, double *out);
 
 /* Deviation storage only: set / read the per-row reference density
  * rho_ref[Ly] (host arrays, finite and > 0).  Setting it invalidates the

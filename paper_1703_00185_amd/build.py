@@ -14,7 +14,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libd2q37.so")
 SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "engine.hip"),
-           os.path.join(CSRC, "lbm_api.cpp"), os.path.join(CSRC, "engine_api.cpp")]
+           os.path.join(CSRC, "lbm_api.cpp"), os.path.join(CSRC, "engine_api.cpp"),
+           os.path.join(CSRC, "noalloc_api.cpp")]
 ARCH = "gfx950"
 
 # -ffp-contract=off: every fused multiply-add in the kernels is an explicit

@@ -358,16 +358,17 @@ __global__ void __launch_bounds__(CONS_THREADS) conservation_final_kernel(
 }
 
 // Gather the populations of n listed sites (coordinates checked on the
-// host): out[l * n + i] = f_l(xy[2i], xy[2i+1]).
+// host): out[l * n + i] = f_l(xs[i], ys[i]).
 template <class C>
 __global__ void __launch_bounds__(256) get_sites_kernel(const typename C::S* __restrict__ f, Geometry g,
-                                                        const int* __restrict__ xy, int n,
+                                                        const int* __restrict__ xs,
+                                                        const int* __restrict__ ys, int n,
                                                         double* __restrict__ out) {
   const C cd{g.ref, g.inv_ref};
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  const int x = xy[2 * i];
-  const int y = xy[2 * i + 1];
+  const int x = xs[i];
+  const int y = ys[i];
   double v[NPOP];
   load_site(g, cd, f, x, y, v);
 #pragma unroll
@@ -611,11 +612,11 @@ hipError_t launch_conservation(const Geometry& g, const void* f, double* partial
   return hipGetLastError();
 }
 
-hipError_t launch_get_sites(const Geometry& g, const void* f, const int* xy, int n, double* out,
-                            hipStream_t s) {
+hipError_t launch_get_sites(const Geometry& g, const void* f, const int* xs, const int* ys, int n,
+                            double* out, hipStream_t s) {
   (void)hipGetLastError();
   D2Q37_STORAGE(g, hipLaunchKernelGGL(get_sites_kernel<C>, dim3((n + 255) / 256), dim3(256), 0, s,
-                                      static_cast<const S*>(f), g, xy, n, out));
+                                      static_cast<const S*>(f), g, xs, ys, n, out));
   return hipGetLastError();
 }
 

@@ -90,8 +90,9 @@ hipError_t launch_fused(const Geometry& g, const void* src, void* dst, const Col
 hipError_t launch_moments(const Geometry& g, const void* f, double* out, hipStream_t s);
 hipError_t launch_conservation(const Geometry& g, const void* f, double* partials, double* result,
                                hipStream_t s);
-hipError_t launch_get_sites(const Geometry& g, const void* f, const int* xy, int n, double* out,
-                            hipStream_t s);
+// out[l * n + i] = f_l(xs[i], ys[i]) for n sites (device arrays).
+hipError_t launch_get_sites(const Geometry& g, const void* f, const int* xs, const int* ys, int n,
+                            double* out, hipStream_t s);
 hipError_t launch_init_rt(const Geometry& g, void* f, const RtParams& p, hipStream_t s);
 hipError_t launch_rt_reference(const Geometry& g, double* ref, double* inv_ref, const RtParams& p,
                                hipStream_t s);

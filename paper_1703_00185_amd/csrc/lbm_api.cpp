@@ -566,19 +566,20 @@ int lbm_get_sites(lbm_handle* h, int32_t n, const int32_t* xs, const int32_t* ys
   const size_t per_site = NPOP * sizeof(double) + 2 * sizeof(int);  // 304 bytes
   if (static_cast<size_t>(n) > h->buf_bytes / per_site)
     return fail(h, LBM_EINVAL, "too many sites for the scratch copy");
+  // x coordinates, then y coordinates
   std::vector<int> xy(2 * static_cast<size_t>(n));
   for (int32_t i = 0; i < n; ++i) {
     if (xs[i] < 0 || xs[i] >= h->geo.lx || ys[i] < 0 || ys[i] >= h->geo.ly)
       return fail(h, LBM_EINVAL, "site " + std::to_string(i) + " outside the lattice");
-    xy[2 * i] = xs[i];
-    xy[2 * i + 1] = ys[i];
+    xy[i] = xs[i];
+    xy[n + i] = ys[i];
   }
   DeviceGuard dg(h->device);
   double* scratch_out = scratch(h);
   int* scratch_xy = reinterpret_cast<int*>(scratch_out + static_cast<size_t>(NPOP) * n);
   LBM_HIP(h, hipMemcpyAsync(scratch_xy, xy.data(), xy.size() * sizeof(int), hipMemcpyHostToDevice,
                             h->stream));
-  LBM_HIP(h, launch_get_sites(h->geo, current(h), scratch_xy, n, scratch_out, h->stream));
+  LBM_HIP(h, launch_get_sites(h->geo, current(h), scratch_xy, scratch_xy + n, n, scratch_out, h->stream));
   LBM_HIP(h, hipMemcpyAsync(out, scratch_out, static_cast<size_t>(NPOP) * n * sizeof(double),
                             hipMemcpyDeviceToHost, h->stream));
   LBM_HIP(h, hipStreamSynchronize(h->stream));

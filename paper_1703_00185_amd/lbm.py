@@ -75,6 +75,7 @@ def load():
         "lbm_get_populations": (c_int, [H, c_void_p]),
         "lbm_set_populations": (c_int, [H, c_void_p]),
         "lbm_get_sites": (c_int, [H, c_int32, c_void_p, c_void_p, c_void_p]),
+        "lbm_get_sites_noalloc": (c_int, [H, c_int32, c_void_p, c_void_p, c_void_p]),
         "lbm_set_reference": (c_int, [H, c_void_p]),
         "lbm_get_reference": (c_int, [H, c_void_p]),
         "lbm_set_timing": (c_int, [H, c_int32]),
@@ -200,6 +201,19 @@ def lbm_get_sites(h, xs, ys) -> np.ndarray:
         raise ValueError("xs and ys must be 1-D arrays of equal length")
     out = np.empty((NPOP, xs.size), dtype=np.float64)
     _check(load().lbm_get_sites(h, xs.size, _ptr(xs), _ptr(ys), _ptr(out)), h)
+    return out
+
+
+LBM_NOALLOC_MAX_SITES = 8192
+
+
+def lbm_get_sites_noalloc(h, xs, ys) -> np.ndarray:
+    xs = np.ascontiguousarray(xs, dtype=np.int32)
+    ys = np.ascontiguousarray(ys, dtype=np.int32)
+    if xs.shape != ys.shape or xs.ndim != 1:
+        raise ValueError("xs and ys must be 1-D arrays of equal length")
+    out = np.empty((NPOP, xs.size), dtype=np.float64)
+    _check(load().lbm_get_sites_noalloc(h, xs.size, _ptr(xs), _ptr(ys), _ptr(out)), h)
     return out
 
 

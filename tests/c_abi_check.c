@@ -118,6 +118,7 @@ int main(void) {
     ok &= lbm_get_populations(NULL, d) == LBM_EINVAL;
     ok &= lbm_set_populations(NULL, d) == LBM_EINVAL;
     ok &= lbm_get_sites(NULL, 1, &xy, &xy, d) == LBM_EINVAL;
+    ok &= lbm_get_sites_noalloc(NULL, 1, &xy, &xy, d) == LBM_EINVAL;
     ok &= lbm_set_reference(NULL, d) == LBM_EINVAL;
     ok &= lbm_get_reference(NULL, d) == LBM_EINVAL;
     ok &= lbm_set_timing(NULL, 1) == LBM_EINVAL;

@@ -123,12 +123,13 @@ hipError_t launch_conservation(const Geometry& g, const void* f, double* partial
   });
   return hipSuccess;
 }
-hipError_t launch_get_sites(const Geometry& g, const void* f, const int* xy, int n, double* out, hipStream_t s) {
+hipError_t launch_get_sites(const Geometry& g, const void* f, const int* xs, const int* ys, int n, double* out,
+                            hipStream_t s) {
   const size_t last = last_of(g);
   enqueue(s, [=] {
     touch_read(f, last);
     for (int i = 0; i < n; ++i)
-      for (int l = 0; l < 37; ++l) out[static_cast<size_t>(l) * n + i] = xy[2 * i] + xy[2 * i + 1];
+      for (int l = 0; l < 37; ++l) out[static_cast<size_t>(l) * n + i] = xs[i] + ys[i];
   });
   return hipSuccess;
 }
