@@ -61,10 +61,15 @@ typedef enum {
 
 /* Storage type of the populations.  Arithmetic is binary64 for all.
  *   LBM_FP32: widened exactly on load, rounded to nearest binary32 on store.
- *   LBM_FP16DEV: binary16 scaled deviation from a per-row reference,
- *     c = w_l rho_ref(y): stored d = f16(f32((f - c) * (w_l^-1 rho_ref(y)^-1))),
- *     read back as c (1 + d).  rho_ref comes from lbm_init_rt (density of
- *     the flat-interface state) or lbm_set_reference.
+ *   LBM_FP16DEV: binary16 scaled deviation from a per-row reference, the
+ *     zero-velocity equilibrium of a reference state with density
+ *     rho_ref(y) per row and temperature T_lo on rows y < y_split, T_hi on
+ *     rows y >= y_split: c = K_l(T(y)) rho_ref(y) (K_l as in
+ *     lbm_wall_factors), stored d = f16(f32((f - c) * (K_l(T(y))^-1 *
+ *     rho_ref(y)^-1))), read back as c (1 + d).  The reference comes from
+ *     lbm_init_rt (the density of the Rayleigh-Taylor state with a flat
+ *     interface, the wall temperatures as the layers, split at the first row
+ *     above the interface) or lbm_set_reference.
  * Bytes per population: 8, 4, 2. */
 typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16DEV = 2 } lbm_storage;
 
@@ -159,7 +164,8 @@ typedef struct {
 int lbm_config_default(lbm_config *cfg, int32_t lx, int32_t ly);
 
 /* Bytes of device memory needed for cfg (two lattice copies with halos,
- * plus the reference rows of deviation storage); 0 if cfg is invalid. */
+ * plus the reference of deviation storage: 16 bytes per row and 256); 0
+ * if cfg is invalid. */
 size_t lbm_required_bytes(const lbm_config *cfg);
 
 /* Bind a lattice to caller memory dev_mem (dev_bytes long) and to the HIP
@@ -238,12 +244,18 @@ int lbm_get_sites(lbm_handle *h, int32_t n, const int32_t *xs, const int32_t *ys
 #define LBM_NOALLOC_MAX_SITES 8192
 int lbm_get_sites_noalloc(lbm_handle *h, int32_t n, const int32_t *xs, const int32_t *ys, double *out);
 
-/* Deviation storage only: set / read the per-row reference density
- * rho_ref[Ly] (host arrays, finite and > 0).  Setting it invalidates the
- * stored state (set populations or init again).  Errors: EINVAL (other
- * storage, bad values), ESTATE (no reference yet, get only). */
-int lbm_set_reference(lbm_handle *h, const double *rho_ref);
-int lbm_get_reference(lbm_handle *h, double *rho_ref);
+/* Deviation storage only: set / read the reference state: rho_ref[Ly]
+ * (host array, finite and > 0), the layer temperatures t_lo (rows
+ * y < y_split) and t_hi (rows y >= y_split), finite, > 0 and with every
+ * K_l(t) > 0, and 0 <= y_split <= Ly (t_lo = t_hi = 1 gives c =
+ * w_l rho_ref(y)).  Setting it uploads rho_ref, 1 / rho_ref and the 32
+ * layer factors into the caller's block after the two lattice copies,
+ * synchronises the stream and invalidates the stored state (set
+ * populations or init again).  On get, t_layers and y_split may be NULL.
+ * Errors: EINVAL (other storage, bad values), ESTATE (no reference yet,
+ * get only). */
+int lbm_set_reference(lbm_handle *h, const double *rho_ref, double t_lo, double t_hi, int32_t y_split);
+int lbm_get_reference(lbm_handle *h, double *rho_ref, double t_layers[2], int32_t *y_split);
 
 /* Per-phase kernel timing with HIP events recorded on the bound stream
  * around every launch while enabled.  lbm_read_timing synchronises the

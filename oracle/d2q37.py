@@ -41,6 +41,13 @@ R8  walls: in propagate, a population whose source lies beyond a wall is
 R9  gravity along -y; bottom wall hot.
 R11 population order: by shell as in R1, then (e_x, e_y) ascending.
 R12 Rayleigh-Taylor initial state in hydrostatic balance (closed form).
+R15 binary16 deviation storage (the reduced-precision form beyond the
+    paper's binary64 code): the deviation is taken from the zero-velocity
+    equilibrium of a reference state with a density per row and two
+    temperature layers (for the Rayleigh-Taylor workload: the density of
+    the state with a flat interface, the wall temperatures below and above
+    the interface), so that it holds little beyond each site's departure
+    from the rest state of its row.
 """
 from __future__ import annotations
 
@@ -317,28 +324,47 @@ def step(f: np.ndarray, cfg) -> np.ndarray:
     return collide(g, cfg.tau, cfg.gx, cfg.gy)
 
 
-def encode_fp16dev(f: np.ndarray, ref: np.ndarray) -> np.ndarray:
-    """Binary16 scaled deviations d of f[37, Lx, Ly] from c = w_l ref(y):
-    q = (f - c) * (w_l^-1 * ref(y)^-1) in binary64, rounded to binary32 and
-    then to binary16 (nearest, ties to even, at each rounding)."""
-    k = constants()
-    c = k.w[:, None, None] * ref[None, None, :]
-    inv = (1.0 / k.w)[:, None, None] * (1.0 / ref)[None, None, :]
-    q = (f - c) * inv
+def fp16dev_reference(rho_ref, t_lo: float, t_hi: float, y_split: int):
+    """Reference of the binary16 deviation storage (reading R15), [37, Ly]
+    twice: c[l, y] = K_l(T(y)) * rho_ref(y) and the encoding factor
+    inv[l, y] = (1 / K_l(T(y))) * (1 / rho_ref(y)), with T(y) = t_lo for
+    y < y_split and t_hi for y >= y_split.  c is the zero-velocity
+    equilibrium (reading R3 at u = 0, the factors of wall_factors) of a
+    reference state with a density per row and two temperature layers.
+    With t_lo = t_hi = 1 it reduces to w_l rho_ref(y)."""
+    rho_ref = np.asarray(rho_ref, dtype=np.float64)
+    ly = rho_ref.size
+    K = {t: np.array(wall_factors(float(t))) for t in (t_lo, t_hi)}
+    c = np.empty((NPOP, ly))
+    inv = np.empty((NPOP, ly))
+    for y in range(ly):
+        k = K[t_lo] if y < y_split else K[t_hi]
+        c[:, y] = k * rho_ref[y]
+        inv[:, y] = (1.0 / k) * (1.0 / rho_ref[y])
+    return c, inv
+
+
+def encode_fp16dev(f: np.ndarray, ref) -> np.ndarray:
+    """Binary16 scaled deviations d of f[37, Lx, Ly] from the reference
+    ref = (c, inv) of fp16dev_reference: q = (f - c) * inv in binary64,
+    rounded to binary32 and then to binary16 (nearest, ties to even, at
+    each rounding)."""
+    c, inv = ref
+    q = (f - c[:, None, :]) * inv[:, None, :]
     return q.astype(np.float32).astype(np.float16)
 
 
-def decode_fp16dev(d: np.ndarray, ref: np.ndarray) -> np.ndarray:
+def decode_fp16dev(d: np.ndarray, ref) -> np.ndarray:
     """Populations c (1 + d) from binary16 deviations (1 + d is exact)."""
-    k = constants()
-    c = k.w[:, None, None] * ref[None, None, :]
-    return c * (1.0 + d.astype(np.float64))
+    c, _ = ref
+    return c[:, None, :] * (1.0 + d.astype(np.float64))
 
 
 def stored(f: np.ndarray, storage: str, ref=None) -> np.ndarray:
     """Values as held in memory and read back: binary64 unchanged; binary32
-    rounded to nearest (ties to even); binary16 deviations from the per-row
-    reference density `ref` (encode_fp16dev, then decode_fp16dev)."""
+    rounded to nearest (ties to even); binary16 deviations from the
+    reference `ref` of fp16dev_reference (encode_fp16dev, then
+    decode_fp16dev)."""
     if storage == "fp64":
         return f
     if storage == "fp32":

@@ -81,43 +81,83 @@ __device__ __forceinline__ void st_nt(S* base, unsigned byte_off, S v) {
 // binary64 population and back.
 //  * binary64: identity.
 //  * binary32: exact widening; rounding to nearest on store.
-//  * binary16 deviation: the element is d = (f - c) / c with the reference
-//    c = w_l rho_ref(y) (a per-row reference density); stored as
-//    d = f16(f32((f - c) * (w_l^-1 * rho_ref(y)^-1))) and read back as
-//    c (1 + d).  1 + d is exact in binary64, so decoding rounds once.
+//  * binary16 deviation: the element is d = (f - c) / c from the reference
+//    c = K_l(T_L(y)) rho_ref(y), the zero-velocity equilibrium of a
+//    reference state with a density per row and two temperature layers
+//    (T_lo below row ysplit, T_hi from it up); stored as
+//    d = f16(f32((f - c) * (K_l(T_L(y))^-1 * rho_ref(y)^-1))) and read
+//    back as c (1 + d).  1 + d is exact in binary64, so decoding rounds
+//    once.
 // kMinWaves: wavefronts per SIMD the fused kernel's register budget must
 // allow (1: no bound).  The binary16 kernel is VALU-bound; capped at 128
-// VGPRs it keeps 4 wavefronts per SIMD and runs 12 % faster than at 155.
+// VGPRs it keeps 4 wavefronts per SIMD.
+// kLayered: the fused kernel gives a wavefront whose rows and pull sources
+// all lie in one temperature layer the codec of that layer
+// (CodecF16DevLayer), whose shell factors are wavefront-uniform.
+// kWrapAlways: the wrapping fused kernel wraps every column's source
+// columns (scalar arithmetic) instead of branching on the 3 + 3 edge
+// columns.
+using ConstD = const __attribute__((address_space(4))) double;
 struct CodecF64 {
   static constexpr int kMinWaves = 1;
+  static constexpr bool kLayered = false;
+  static constexpr bool kWrapAlways = false;
   using S = double;
-  const double* ref;
-  const double* inv_ref;
+  static __device__ CodecF64 of(const Geometry&) { return {}; }
   __device__ double dec(S v, int, int) const { return v; }
   __device__ S enc(double f, int, int) const { return f; }
 };
 struct CodecF32 {
   static constexpr int kMinWaves = 1;
+  static constexpr bool kLayered = false;
+  static constexpr bool kWrapAlways = false;
   using S = float;
-  const double* ref;
-  const double* inv_ref;
+  static __device__ CodecF32 of(const Geometry&) { return {}; }
   __device__ double dec(S v, int, int) const { return static_cast<double>(v); }
   __device__ S enc(double f, int, int) const { return static_cast<float>(f); }
 };
+// Any rows: the layer is chosen per lane.
 struct CodecF16Dev {
   static constexpr int kMinWaves = 4;
+  static constexpr bool kLayered = true;
+  static constexpr bool kWrapAlways = true;
   using S = _Float16;
   const double* ref;
   const double* inv_ref;
+  ConstD* kf;
+  int ysplit;
+  static __device__ CodecF16Dev of(const Geometry& g) { return {g.ref, g.inv_ref, (ConstD*)(g.kf), g.ysplit}; }
+  // the factors of both layers are scalar; the row picks one per lane
+  __device__ double factor(int y, int k_lo, int k_hi) const { return y >= ysplit ? kf[k_hi] : kf[k_lo]; }
   __device__ double dec(S v, int l, int y) const {
-    const double c = weight_of(l) * ref[y];
+    const int s = shell_of(l);
+    const double c = factor(y, KF_LO + s, KF_HI + s) * ref[y];
     // c (1 + d) rounded once: 1 + d is exact, so the fused multiply-add
     // c d + c is the same correctly rounded value
     return fma(c, static_cast<double>(static_cast<float>(v)), c);
   }
   __device__ S enc(double f, int l, int y) const {
-    const double c = weight_of(l) * ref[y];
-    const double q = (f - c) * (inv_weight_of(l) * inv_ref[y]);
+    const int s = shell_of(l);
+    const double c = factor(y, KF_LO + s, KF_HI + s) * ref[y];
+    const double q = (f - c) * (factor(y, KF_INV_LO + s, KF_INV_HI + s) * inv_ref[y]);
+    return static_cast<_Float16>(static_cast<float>(q));
+  }
+};
+// Rows of one temperature layer: k points at that layer's K_s, kinv at its
+// 1 / K_s (wavefront-uniform).  Same arithmetic as CodecF16Dev.
+struct CodecF16DevLayer {
+  using S = _Float16;
+  const double* ref;
+  const double* inv_ref;
+  ConstD* k;
+  ConstD* kinv;
+  __device__ double dec(S v, int l, int y) const {
+    const double c = k[shell_of(l)] * ref[y];
+    return fma(c, static_cast<double>(static_cast<float>(v)), c);
+  }
+  __device__ S enc(double f, int l, int y) const {
+    const double c = k[shell_of(l)] * ref[y];
+    const double q = (f - c) * (kinv[shell_of(l)] * inv_ref[y]);
     return static_cast<_Float16>(static_cast<float>(q));
   }
 };

@@ -82,7 +82,7 @@ __device__ __forceinline__ void gather_wrap_wall(SlotView& d, const C& cd,
 template <class C>
 __device__ __forceinline__ void step_tile(SlotView& d, int x, int yw) {
   using S = typename C::S;
-  const C cd{nullptr, nullptr};
+  const C cd{};
   const GLOBAL_AS S* src = (const GLOBAL_AS S*)(d.buf[d.cur]);
   GLOBAL_AS S* dst = (GLOBAL_AS S*)(d.buf[d.cur ^ 1]);
   const int ywave = yw * WAVE;

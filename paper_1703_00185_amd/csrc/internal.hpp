@@ -23,7 +23,9 @@ struct lbm_handle {
   hipStream_t stream = nullptr;
   int device = 0;
   bool ready = false;
-  bool has_ref = false;  // deviation storage: reference density set
+  bool has_ref = false;  // deviation storage: reference state set
+  std::vector<double> rho_ref;          // that state (host copies): density per row,
+  double t_layers[2] = {1.0, 1.0};      // temperatures below / from geo.ysplit
   d2q37::CollideParams cp{};
   d2q37::WallParams wp{};
   std::string err;

@@ -33,11 +33,12 @@ template <int BLOCK>
 __device__ __forceinline__ void lane_site(const Geometry& g, const ColumnSet& cols, int& x, int& y,
                                           int& ywave) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int c = tile / g.ny_blocks;
+  const int nyb = cols.nyb > 0 ? cols.nyb : g.ny_blocks;
+  const int c = tile / nyb;
   x = c < cols.na ? cols.xa + c : cols.xb + (c - cols.na);
-  const int yb = tile - c * g.ny_blocks;
-  y = yb * BLOCK + threadIdx.x;
-  ywave = yb * BLOCK + (threadIdx.x & ~(WAVE - 1));
+  const int yb = tile - c * nyb;
+  y = cols.y0 + yb * BLOCK + threadIdx.x;
+  ywave = cols.y0 + yb * BLOCK + (threadIdx.x & ~(WAVE - 1));
 }
 
 // True (wavefront-uniform) when every row this wavefront pulls from lies
@@ -196,7 +197,7 @@ __global__ void __launch_bounds__(256) pbc_kernel(S* __restrict__ f, Geometry g)
 template <class C, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) propagate_kernel(const typename C::S* __restrict__ src,
                                                           typename C::S* __restrict__ dst, Geometry g) {
-  const C cd{g.ref, g.inv_ref};
+  const C cd = C::of(g);
   int x, y, ywave;
   lane_site<BLOCK>(g, ColumnSet{0, g.lx, 0}, x, y, ywave);
   if (ywave >= g.ly) return;  // whole wavefront beyond the lattice (no barrier follows)
@@ -212,7 +213,7 @@ __global__ void __launch_bounds__(BLOCK) propagate_kernel(const typename C::S* _
 // bc (Sec. 4): thermal walls, in place, on the 3 bottom and 3 top rows.
 template <class C>
 __global__ void __launch_bounds__(256) bc_kernel(typename C::S* __restrict__ f, Geometry g, WallParams w) {
-  const C cd{g.ref, g.inv_ref};
+  const C cd = C::of(g);
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= g.lx * 2 * WALL_ROWS) return;
   const int x = t / (2 * WALL_ROWS);
@@ -230,7 +231,7 @@ template <class C, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) collide_kernel(const typename C::S* __restrict__ src,
                                                         typename C::S* __restrict__ dst, Geometry g,
                                                         CollideParams c) {
-  const C cd{g.ref, g.inv_ref};
+  const C cd = C::of(g);
   int x, y, ywave;
   lane_site<BLOCK>(g, ColumnSet{0, g.lx, 0}, x, y, ywave);
   if (y >= g.ly) return;
@@ -240,37 +241,93 @@ __global__ void __launch_bounds__(BLOCK) collide_kernel(const typename C::S* __r
   store_column_site(g, cd, dst, x, y, f);
 }
 
+// One site of the fused step (below), with the codec cd.
+template <class C, int BLOCK, bool WRAP, bool BAND>
+__device__ __forceinline__ void fused_site(const Geometry& g, const C& cd, const typename C::S* __restrict__ src,
+                                           typename C::S* __restrict__ dst, const CollideParams& c,
+                                           const WallParams& w, const ColumnSet& cols, int x, int y,
+                                           int ywave) {
+  if (ywave >= g.ly) return;  // whole wavefront beyond the lattice (no barrier follows)
+  double f[NPOP];
+  if constexpr (C::kLayered) {
+    // The layer of the reference is uniform over a wavefront unless its
+    // rows or its pull sources (3 rows beyond) reach both layers: those
+    // wavefronts (at most two per column) are left to the band launch,
+    // which takes the general codec; every other one takes the codec of
+    // its layer, whose shell factors are wavefront-uniform.
+    const int yw = __builtin_amdgcn_readfirstlane(ywave);  // uniform: scalar branches and loads
+    const int lowest = max(yw - WALL_ROWS, 0);
+    const int highest = min(yw + WAVE + WALL_ROWS - 1, g.ly - 1);
+    const bool straddles = lowest < g.ysplit && highest >= g.ysplit;
+    if constexpr (BAND) {
+      if (!straddles) return;
+      const int yc = y < g.ly ? y : g.ly - 1;
+      gather_wall<WRAP>(g, cd, src, x, yc, f);
+      if (yc < WALL_ROWS || yc >= g.ly - WALL_ROWS) thermalise(f, yc < WALL_ROWS, w);
+      collide_site(f, c);
+      if (y < g.ly) store_column_site(g, cd, dst, x, y, f);
+      return;
+    }
+    if (straddles) return;
+    const bool hi = yw >= g.ysplit;
+    const ConstD* kf = (ConstD*)(g.kf);
+    const CodecF16DevLayer lc{g.ref, g.inv_ref, kf + (hi ? KF_HI : KF_LO), kf + (hi ? KF_INV_HI : KF_INV_LO)};
+    if (interior_wave(g, ywave)) {
+      gather_interior<WRAP>(g, lc, src, x, y, f);
+    } else {
+      const int yc = y < g.ly ? y : g.ly - 1;
+      gather_wall<WRAP>(g, lc, src, x, yc, f);
+      if (yc < WALL_ROWS || yc >= g.ly - WALL_ROWS) thermalise(f, yc < WALL_ROWS, w);
+    }
+    collide_site(f, c);
+    if (y < g.ly) store_column_site(g, lc, dst, x, y, f);
+    return;
+  }
+  if constexpr (C::kWrapAlways) {
+    // every column wraps its 7 source columns (scalar arithmetic: the
+    // column is uniform over the work-group), one gather code path
+    if (interior_wave(g, ywave)) {
+      gather_interior<WRAP>(g, cd, src, x, y, f);
+    } else {
+      const int yc = y < g.ly ? y : g.ly - 1;
+      gather_wall<WRAP>(g, cd, src, x, yc, f);
+      if (yc < WALL_ROWS || yc >= g.ly - WALL_ROWS) thermalise(f, yc < WALL_ROWS, w);
+    }
+  } else {
+    // only the 3 + 3 edge columns pull across the periodic boundary; the
+    // column is uniform over the work-group, so this is one scalar branch
+    // and every other column runs the plain gather
+    const bool edge = WRAP && (x < HALO || x >= g.lx - HALO);
+    if (interior_wave(g, ywave)) {
+      if (edge) gather_interior<true>(g, cd, src, x, y, f);
+      else gather_interior<false>(g, cd, src, x, y, f);
+    } else {
+      const int yc = y < g.ly ? y : g.ly - 1;
+      if (edge) gather_wall<true>(g, cd, src, x, yc, f);
+      else gather_wall<false>(g, cd, src, x, yc, f);
+      if (yc < WALL_ROWS || yc >= g.ly - WALL_ROWS) thermalise(f, yc < WALL_ROWS, w);
+    }
+  }
+  collide_site(f, c);
+  if (y < g.ly) store_column_site(g, cd, dst, x, y, f);
+}
+
 // propagate + bc + collide in registers: one read and one write of every
 // population per step (the fusion the paper applies in Sec. 5, here on
 // every row, walls included, since bc is site-local).  WRAP: periodic x by
 // wrapping source columns (no halo read, so no pbc launch is needed);
-// else the halo columns are read.  Binary16-deviation lattices use the
-// non-wrapping form only: with both gathers it does not fit the register
-// bound of its codec (kMinWaves) without spilling.
-template <class C, int BLOCK, bool WRAP>
-__global__ void __launch_bounds__(BLOCK, C::kMinWaves) fused_kernel(const typename C::S* __restrict__ src,
+// else the halo columns are read.
+// BAND: the launch over the wavefronts that straddle the layers of the
+// binary16 deviation reference (see fused_site); a few wavefronts per
+// column, so it takes no register bound.
+template <class C, int BLOCK, bool WRAP, bool BAND = false>
+__global__ void __launch_bounds__(BLOCK, BAND ? 1 : C::kMinWaves) fused_kernel(const typename C::S* __restrict__ src,
                                                       typename C::S* __restrict__ dst, Geometry g,
                                                       CollideParams c, WallParams w, ColumnSet cols) {
-  const C cd{g.ref, g.inv_ref};
   int x, y, ywave;
   lane_site<BLOCK>(g, cols, x, y, ywave);
-  if (ywave >= g.ly) return;  // whole wavefront beyond the lattice (no barrier follows)
-  double f[NPOP];
-  // only the 3 + 3 edge columns pull across the periodic boundary; the
-  // column is uniform over the work-group, so this is one scalar branch
-  // and every other column runs the plain gather
-  const bool edge = WRAP && (x < HALO || x >= g.lx - HALO);
-  if (interior_wave(g, ywave)) {
-    if (edge) gather_interior<true>(g, cd, src, x, y, f);
-    else gather_interior<false>(g, cd, src, x, y, f);
-  } else {
-    const int yc = y < g.ly ? y : g.ly - 1;
-    if (edge) gather_wall<true>(g, cd, src, x, yc, f);
-    else gather_wall<false>(g, cd, src, x, yc, f);
-    if (yc < WALL_ROWS || yc >= g.ly - WALL_ROWS) thermalise(f, yc < WALL_ROWS, w);
-  }
-  collide_site(f, c);
-  if (y < g.ly) store_column_site(g, cd, dst, x, y, f);
+  const C cd = C::of(g);
+  fused_site<C, BLOCK, WRAP, BAND>(g, cd, src, dst, c, w, cols, x, y, ywave);
 }
 
 // Per-site rho, ux, uy, T into out[4][lx][ly] (Sec. 2 moment definitions;
@@ -278,7 +335,7 @@ __global__ void __launch_bounds__(BLOCK, C::kMinWaves) fused_kernel(const typena
 template <class C>
 __global__ void __launch_bounds__(256) moments_kernel(const typename C::S* __restrict__ src,
                                                       double* __restrict__ out, Geometry g) {
-  const C cd{g.ref, g.inv_ref};
+  const C cd = C::of(g);
   const long long n = static_cast<long long>(g.lx) * g.ly;
   const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
   if (i >= n) return;
@@ -317,7 +374,7 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
 template <class C>
 __global__ void __launch_bounds__(CONS_THREADS) conservation_partial_kernel(
     const typename C::S* __restrict__ src, Geometry g, double* __restrict__ partials) {
-  const C cd{g.ref, g.inv_ref};
+  const C cd = C::of(g);
   __shared__ double lds[CONS_THREADS / WAVE];
   const long long n = static_cast<long long>(g.lx) * g.ly;
   double acc[CONS_FIELDS] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -364,7 +421,7 @@ __global__ void __launch_bounds__(256) get_sites_kernel(const typename C::S* __r
                                                         const int* __restrict__ xs,
                                                         const int* __restrict__ ys, int n,
                                                         double* __restrict__ out) {
-  const C cd{g.ref, g.inv_ref};
+  const C cd = C::of(g);
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const int x = xs[i];
@@ -399,7 +456,7 @@ __device__ __forceinline__ void rt_fields(const RtParams& p, int y, double h, do
 template <class C>
 __global__ void __launch_bounds__(256) init_rt_kernel(typename C::S* __restrict__ f, Geometry g,
                                                       RtParams p) {
-  const C cd{g.ref, g.inv_ref};
+  const C cd = C::of(g);
   const long long n = static_cast<long long>(g.lx) * g.ly;
   const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
   if (i >= n) return;
@@ -421,17 +478,17 @@ __global__ void __launch_bounds__(256) init_rt_kernel(typename C::S* __restrict_
   }
 }
 
-// Per-row reference density of the deviation storage: the density of the
-// Rayleigh-Taylor state with a flat interface, and its reciprocal.
-__global__ void __launch_bounds__(256) rt_reference_kernel(double* __restrict__ ref,
-                                                           double* __restrict__ inv_ref, int ly,
+// Reference state of the deviation storage, per row: density and
+// temperature of the Rayleigh-Taylor state with a flat interface.
+__global__ void __launch_bounds__(256) rt_reference_kernel(double* __restrict__ rho_out,
+                                                           double* __restrict__ temp_out, int ly,
                                                            RtParams p) {
   const int y = blockIdx.x * 256 + threadIdx.x;
   if (y >= ly) return;
   double rho, temp;
   rt_fields(p, y, 0.0, rho, temp);
-  ref[y] = rho;
-  inv_ref[y] = 1.0 / rho;
+  rho_out[y] = rho;
+  temp_out[y] = temp;
 }
 
 // Host-array transfers through the codec: one population at a time
@@ -440,7 +497,7 @@ template <class C>
 __global__ void __launch_bounds__(256) encode_population_kernel(const double* __restrict__ in,
                                                            typename C::S* __restrict__ f,
                                                            Geometry g, int l) {
-  const C cd{g.ref, g.inv_ref};
+  const C cd = C::of(g);
   const long long n = static_cast<long long>(g.lx) * g.ly;
   const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
   if (i >= n) return;
@@ -452,7 +509,7 @@ __global__ void __launch_bounds__(256) encode_population_kernel(const double* __
 template <class C>
 __global__ void __launch_bounds__(256) decode_population_kernel(const typename C::S* __restrict__ f,
                                                            double* __restrict__ out, Geometry g, int l) {
-  const C cd{g.ref, g.inv_ref};
+  const C cd = C::of(g);
   const long long n = static_cast<long long>(g.lx) * g.ly;
   const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
   if (i >= n) return;
@@ -565,20 +622,56 @@ hipError_t launch_fused(const Geometry& g, const void* src, void* dst, const Col
   const ColumnSet cs = cols ? *cols : all;
   const int ncols = cs.na + (cols ? cs.nb : 0);
   if (ncols <= 0) return hipSuccess;
+  hipError_t e = launch_fused_rows(g, src, dst, c, w, s, cs, ncols, g.ny_blocks, wrap);
+  if (e != hipSuccess || g.storage != STORAGE_F16DEV || g.ysplit <= 0 || g.ysplit >= g.ly) return e;
+  // the wavefronts that straddle the reference's temperature layers: first
+  // rows y0 (multiples of 64) with y0 - 3 < ysplit <= y0 + 66
+  const int first = std::max(0, (g.ysplit - WALL_ROWS) / WAVE * WAVE);
+  const int last = std::min((g.ly - 1) / WAVE * WAVE, (g.ysplit + WALL_ROWS - 1) / WAVE * WAVE);
+  ColumnSet band = cs;
+  band.band = 1;
+  band.y0 = first;
+  band.nyb = (last + WAVE - first + g.block - 1) / g.block;
+  return launch_fused_rows(g, src, dst, c, w, s, band, ncols, band.nyb, wrap);
+}
+
+hipError_t launch_fused_rows(const Geometry& g, const void* src, void* dst, const CollideParams& c,
+                             const WallParams& w, hipStream_t s, const ColumnSet& cs, int ncols, int nyb,
+                             bool wrap) {
   (void)hipGetLastError();
+  if (cs.band) {
+    if (g.storage != STORAGE_F16DEV) return hipErrorInvalidValue;
+    using C = CodecF16Dev;
+    using S = C::S;
+    if (wrap) {
+      D2Q37_BLOCKS(g, hipLaunchKernelGGL((fused_kernel<C, BS, true, true>), dim3(ncols * nyb), dim3(BS), 0, s,
+                                         static_cast<const S*>(src), static_cast<S*>(dst), g, c, w, cs));
+    } else {
+      D2Q37_BLOCKS(g, hipLaunchKernelGGL((fused_kernel<C, BS, false, true>), dim3(ncols * nyb), dim3(BS), 0, s,
+                                         static_cast<const S*>(src), static_cast<S*>(dst), g, c, w, cs));
+    }
+    return hipGetLastError();
+  }
   if (wrap) {
-    switch (g.storage) {  // binary64 and binary32 only (see fused_kernel)
+    switch (g.storage) {
       case STORAGE_F64: {
         using C = CodecF64;
         using S = C::S;
-        D2Q37_BLOCKS(g, hipLaunchKernelGGL((fused_kernel<C, BS, true>), dim3(ncols * g.ny_blocks), dim3(BS),
+        D2Q37_BLOCKS(g, hipLaunchKernelGGL((fused_kernel<C, BS, true>), dim3(ncols * nyb), dim3(BS),
                                            0, s, static_cast<const S*>(src), static_cast<S*>(dst), g, c, w, cs));
         break;
       }
       case STORAGE_F32: {
         using C = CodecF32;
         using S = C::S;
-        D2Q37_BLOCKS(g, hipLaunchKernelGGL((fused_kernel<C, BS, true>), dim3(ncols * g.ny_blocks), dim3(BS),
+        D2Q37_BLOCKS(g, hipLaunchKernelGGL((fused_kernel<C, BS, true>), dim3(ncols * nyb), dim3(BS),
+                                           0, s, static_cast<const S*>(src), static_cast<S*>(dst), g, c, w, cs));
+        break;
+      }
+      case STORAGE_F16DEV: {
+        using C = CodecF16Dev;
+        using S = C::S;
+        D2Q37_BLOCKS(g, hipLaunchKernelGGL((fused_kernel<C, BS, true>), dim3(ncols * nyb), dim3(BS),
                                            0, s, static_cast<const S*>(src), static_cast<S*>(dst), g, c, w, cs));
         break;
       }
@@ -586,7 +679,7 @@ hipError_t launch_fused(const Geometry& g, const void* src, void* dst, const Col
         return hipErrorInvalidValue;
     }
   } else {
-    D2Q37_DISPATCH(g, hipLaunchKernelGGL((fused_kernel<C, BS, false>), dim3(ncols * g.ny_blocks), dim3(BS),
+    D2Q37_DISPATCH(g, hipLaunchKernelGGL((fused_kernel<C, BS, false>), dim3(ncols * nyb), dim3(BS),
                                          0, s, static_cast<const S*>(src), static_cast<S*>(dst), g, c, w, cs));
   }
   return hipGetLastError();
@@ -641,10 +734,10 @@ hipError_t launch_probe(int mode, const void* src, void* dst, size_t n16, int sh
   return hipGetLastError();
 }
 
-hipError_t launch_rt_reference(const Geometry& g, double* ref, double* inv_ref, const RtParams& p,
+hipError_t launch_rt_reference(const Geometry& g, double* rho, double* temp, const RtParams& p,
                                hipStream_t s) {
   (void)hipGetLastError();
-  hipLaunchKernelGGL(rt_reference_kernel, dim3((g.ly + 255) / 256), dim3(256), 0, s, ref, inv_ref, g.ly, p);
+  hipLaunchKernelGGL(rt_reference_kernel, dim3((g.ly + 255) / 256), dim3(256), 0, s, rho, temp, g.ly, p);
   return hipGetLastError();
 }
 

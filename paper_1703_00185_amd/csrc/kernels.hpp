@@ -32,9 +32,19 @@ struct Geometry {
   int ny_blocks;     // ceil(ly / block)
   long long pstride; // elements between populations l and l + 1 of a site
   long long cstride; // elements between columns X and X + 1
-  const double* ref;      // per-row reference density (deviation storage)
-  const double* inv_ref;  // its reciprocal
+  // deviation storage: the reference density per row and its reciprocal,
+  // and the shell factors kf[KF_LEN] of the two temperature layers (rows
+  // y < ysplit and y >= ysplit)
+  const double* ref;
+  const double* inv_ref;
+  const double* kf;
+  int ysplit;
 };
+
+// Shell factors of the deviation-storage reference: K_s(T_lo), K_s(T_hi),
+// 1 / K_s(T_lo), 1 / K_s(T_hi), NSHELL doubles each.
+constexpr int KF_LO = 0, KF_HI = NSHELL, KF_INV_LO = 2 * NSHELL, KF_INV_HI = 3 * NSHELL;
+constexpr int KF_LEN = 4 * NSHELL;
 
 // Scalars of the collision (Eqs. 4-6): omega = 1/tau, the shift tau*g of
 // the velocity and tau^2 |g|^2 / 2 of the temperature.
@@ -52,10 +62,16 @@ struct WallParams {
 };
 
 // Columns covered by a lattice launch: na columns from xa, then nb
-// columns from xb (nb is used by the host only, to size the grid).
+// columns from xb (nb is used by the host only, to size the grid).  band:
+// a launch of the fused kernel over only the wavefronts that straddle the
+// temperature layers of the binary16 deviation reference, rows from y0 in
+// nyb work-group tiles (0: every other wavefront, rows from 0).
 struct ColumnSet {
   int xa, na, xb;
   int nb = 0;
+  int band = 0;
+  int y0 = 0;
+  int nyb = 0;  // 0: the geometry's ny_blocks
 };
 
 // Rayleigh-Taylor initial state parameters.
@@ -81,12 +97,17 @@ hipError_t launch_bc(const Geometry& g, void* f, const WallParams& w, hipStream_
 hipError_t launch_collide(const Geometry& g, const void* src, void* dst, const CollideParams& c,
                           hipStream_t s);
 // cols = nullptr: every column; else the two column ranges of *cols.
-// wrap: periodic x by wrapping source columns (reads no halo column;
-// binary64 and binary32 storage only); else the halo columns written by
-// pbc are read.
+// wrap: periodic x by wrapping source columns (reads no halo column);
+// else the halo columns written by pbc are read.
 hipError_t launch_fused(const Geometry& g, const void* src, void* dst, const CollideParams& c,
                         const WallParams& w, hipStream_t s, const ColumnSet* cols = nullptr,
                         bool wrap = false);
+// One launch of the fused kernel over ncols columns and nyb work-group
+// tiles per column (launch_fused adds the band launch of binary16
+// deviation lattices).
+hipError_t launch_fused_rows(const Geometry& g, const void* src, void* dst, const CollideParams& c,
+                             const WallParams& w, hipStream_t s, const ColumnSet& cs, int ncols, int nyb,
+                             bool wrap);
 hipError_t launch_moments(const Geometry& g, const void* f, double* out, hipStream_t s);
 hipError_t launch_conservation(const Geometry& g, const void* f, double* partials, double* result,
                                hipStream_t s);
@@ -94,7 +115,9 @@ hipError_t launch_conservation(const Geometry& g, const void* f, double* partial
 hipError_t launch_get_sites(const Geometry& g, const void* f, const int* xs, const int* ys, int n,
                             double* out, hipStream_t s);
 hipError_t launch_init_rt(const Geometry& g, void* f, const RtParams& p, hipStream_t s);
-hipError_t launch_rt_reference(const Geometry& g, double* ref, double* inv_ref, const RtParams& p,
+// Density and temperature of the flat-interface Rayleigh-Taylor state per
+// row (the deviation-storage reference state), into rho[ly] and temp[ly].
+hipError_t launch_rt_reference(const Geometry& g, double* rho, double* temp, const RtParams& p,
                                hipStream_t s);
 hipError_t launch_encode_population(const Geometry& g, const double* in, void* f, int l, hipStream_t s);
 hipError_t launch_decode_population(const Geometry& g, const void* f, double* out, int l, hipStream_t s);

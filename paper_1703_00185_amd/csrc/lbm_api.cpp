@@ -4,6 +4,7 @@
 // caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -26,8 +27,8 @@ long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
 struct Layout {
   Geometry geo;
   size_t buf_bytes;
-  size_t ref_bytes;  // deviation storage: rho_ref[ly] and 1/rho_ref[ly], each 256-aligned
-  size_t total() const { return 2 * buf_bytes + 2 * ref_bytes; }
+  size_t ref_bytes;  // deviation storage: rho_ref[ly], 1/rho_ref[ly], the layer factors
+  size_t total() const { return 2 * buf_bytes + ref_bytes; }
 };
 
 // Default work-group size: the fastest measured on the 2048 x 8192 fused
@@ -95,7 +96,9 @@ int make_layout(const lbm_config* c, Layout* out, std::string* why) {
   }
   out->geo = g;
   out->buf_bytes = static_cast<size_t>(round_up(elems * elem_bytes(g), 256));
-  out->ref_bytes = g.storage == STORAGE_F16DEV ? static_cast<size_t>(round_up(8LL * c->ly, 256)) : 0;
+  out->ref_bytes = g.storage == STORAGE_F16DEV
+                       ? static_cast<size_t>(2 * round_up(8LL * c->ly, 256) + round_up(8LL * KF_LEN, 256))
+                       : 0;
   // host transfers stage one population ([lx][ly] binary64) in the idle copy
   if (static_cast<size_t>(8) * c->lx * c->ly > out->buf_bytes)
     return *why = "internal: staging does not fit", LBM_EINVAL;
@@ -147,13 +150,8 @@ int ensure_side(lbm_handle* h) {
   return LBM_OK;
 }
 
-// One step of the fused path: one launch that wraps x; binary16-deviation
-// lattices refresh the halo columns first and run the non-wrapping kernel.
-int fused_step(lbm_handle* h) {
-  int rc = h->geo.storage == STORAGE_F16DEV ? run_phase(h, LBM_PHASE_PBC) : LBM_OK;
-  if (rc == LBM_OK) rc = run_phase(h, LBM_PHASE_FUSED);
-  return rc;
-}
+// One step of the fused path: one launch that wraps x.
+int fused_step(lbm_handle* h) { return run_phase(h, LBM_PHASE_FUSED); }
 
 // n steps of the region path.  Step k runs the fused kernel on the bulk
 // columns 3..Lx-4 (which pull from no halo) on the caller's stream, and pbc
@@ -225,10 +223,9 @@ int run_phase(lbm_handle* h, int phase) {
       rc = timed(h, phase, [&] { return launch_collide(g, current(h), other(h), h->cp, h->stream); });
       if (rc == LBM_OK) h->cur ^= 1;
       break;
-    case LBM_PHASE_FUSED:  // periodic x by wrapping (binary16 deviations: halo read)
+    case LBM_PHASE_FUSED:  // periodic x by wrapping
       rc = timed(h, phase, [&] {
-        return launch_fused(g, current(h), other(h), h->cp, h->wp, h->stream, nullptr,
-                            g.storage != STORAGE_F16DEV);
+        return launch_fused(g, current(h), other(h), h->cp, h->wp, h->stream, nullptr, true);
       });
       if (rc == LBM_OK) h->cur ^= 1;
       break;
@@ -236,6 +233,49 @@ int run_phase(lbm_handle* h, int phase) {
       return fail(h, LBM_EINVAL, "unknown phase");
   }
   return rc;
+}
+
+// Build and upload the deviation-storage reference from the reference
+// state: density rho(y) per row, temperature t_lo on rows y < ysplit and
+// t_hi on rows y >= ysplit.  Uploads rho, 1 / rho and the shell factors
+// K_s(t_lo), K_s(t_hi) (the wall factor of the first population of shell
+// s: the zero-velocity equilibrium per unit density) and their
+// reciprocals, each rounded once.  Keeps host copies for
+// lbm_get_reference.  Synchronises the handle's stream.
+int set_reference_table(lbm_handle* h, const double* rho, double t_lo, double t_hi, int ysplit) {
+  const int ly = h->geo.ly;
+  if (ysplit < 0 || ysplit > ly) return fail(h, LBM_EINVAL, "y_split must be in [0, Ly]");
+  if (!std::isfinite(t_lo) || !(t_lo > 0.0) || !std::isfinite(t_hi) || !(t_hi > 0.0))
+    return fail(h, LBM_EINVAL, "layer temperatures must be finite and > 0");
+  std::vector<double> rows(2 * static_cast<size_t>(ly));
+  for (int y = 0; y < ly; ++y) {
+    if (!std::isfinite(rho[y]) || !(rho[y] > 0.0)) return fail(h, LBM_EINVAL, "rho_ref must be finite and > 0");
+    rows[y] = rho[y];
+    rows[ly + y] = 1.0 / rho[y];
+  }
+  std::vector<double> kf(KF_LEN);
+  for (int sh = 0; sh < NSHELL; ++sh) {
+    kf[KF_LO + sh] = wall_factor(SHELL_START[sh], t_lo);
+    kf[KF_HI + sh] = wall_factor(SHELL_START[sh], t_hi);
+    if (!std::isfinite(kf[KF_LO + sh]) || !(kf[KF_LO + sh] > 0.0) || !std::isfinite(kf[KF_HI + sh]) ||
+        !(kf[KF_HI + sh] > 0.0))
+      return fail(h, LBM_EINVAL, "the zero-velocity equilibrium is not positive at the layer temperatures");
+    kf[KF_INV_LO + sh] = 1.0 / kf[KF_LO + sh];
+    kf[KF_INV_HI + sh] = 1.0 / kf[KF_HI + sh];
+  }
+  LBM_HIP(h, hipMemcpyAsync(const_cast<double*>(h->geo.ref), rows.data(), ly * sizeof(double),
+                            hipMemcpyHostToDevice, h->stream));
+  LBM_HIP(h, hipMemcpyAsync(const_cast<double*>(h->geo.inv_ref), rows.data() + ly, ly * sizeof(double),
+                            hipMemcpyHostToDevice, h->stream));
+  LBM_HIP(h, hipMemcpyAsync(const_cast<double*>(h->geo.kf), kf.data(), KF_LEN * sizeof(double),
+                            hipMemcpyHostToDevice, h->stream));
+  LBM_HIP(h, hipStreamSynchronize(h->stream));
+  h->geo.ysplit = ysplit;
+  h->rho_ref.assign(rho, rho + ly);
+  h->t_layers[0] = t_lo;
+  h->t_layers[1] = t_hi;
+  h->has_ref = true;
+  return LBM_OK;
 }
 
 }  // namespace
@@ -301,9 +341,11 @@ int lbm_create(const lbm_config* cfg, void* dev_mem, size_t dev_bytes, void* str
   h->buf[0] = static_cast<char*>(dev_mem);
   h->buf[1] = static_cast<char*>(dev_mem) + L.buf_bytes;
   if (L.ref_bytes) {
-    h->geo.ref = reinterpret_cast<const double*>(static_cast<char*>(dev_mem) + 2 * L.buf_bytes);
-    h->geo.inv_ref = reinterpret_cast<const double*>(static_cast<char*>(dev_mem) + 2 * L.buf_bytes +
-                                                     L.ref_bytes);
+    char* r = static_cast<char*>(dev_mem) + 2 * L.buf_bytes;
+    const size_t row_bytes = static_cast<size_t>(round_up(8LL * cfg->ly, 256));
+    h->geo.ref = reinterpret_cast<const double*>(r);
+    h->geo.inv_ref = reinterpret_cast<const double*>(r + row_bytes);
+    h->geo.kf = reinterpret_cast<const double*>(r + 2 * row_bytes);
   }
   h->stream = static_cast<hipStream_t>(stream);
   h->device = attr.device;
@@ -352,9 +394,19 @@ int lbm_init_rt(lbm_handle* h, const lbm_rt_params* rt) {
   }
   DeviceGuard dg(h->device);
   if (h->geo.storage == STORAGE_F16DEV) {
-    LBM_HIP(h, launch_rt_reference(h->geo, const_cast<double*>(h->geo.ref),
-                                   const_cast<double*>(h->geo.inv_ref), p, h->stream));
-    h->has_ref = true;
+    // the reference state: the density of the flat-interface state, on
+    // the device with the same closed form as the initial state; the wall
+    // temperatures as the layers, split at the first row above the
+    // interface
+    const int ly = h->geo.ly;
+    double* rows = scratch(h);
+    std::vector<double> rho(ly);
+    LBM_HIP(h, launch_rt_reference(h->geo, rows, rows + ly, p, h->stream));
+    LBM_HIP(h, hipMemcpyAsync(rho.data(), rows, ly * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    LBM_HIP(h, hipStreamSynchronize(h->stream));
+    const int ysplit = static_cast<int>(std::min<double>(std::max(std::ceil(rt->y_center), 0.0), ly));
+    const int rc = set_reference_table(h, rho.data(), h->cfg.t_bottom, h->cfg.t_top, ysplit);
+    if (rc != LBM_OK) return rc;
   }
   LBM_HIP(h, launch_init_rt(h->geo, current(h), p, h->stream));
   h->ready = true;
@@ -518,40 +570,30 @@ int lbm_set_populations(lbm_handle* h, const double* host) {
   return LBM_OK;
 }
 
-int lbm_set_reference(lbm_handle* h, const double* rho_ref) {
+int lbm_set_reference(lbm_handle* h, const double* rho_ref, double t_lo, double t_hi, int32_t y_split) {
   if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
   if (h->engine) return fail(h, LBM_ESTATE, "lattice is stepped by an engine (remove it first)");
   if (!rho_ref) return fail(h, LBM_EINVAL, "rho_ref is NULL");
   if (h->geo.storage != STORAGE_F16DEV)
-    return fail(h, LBM_EINVAL, "a reference density exists only for LBM_FP16DEV storage");
-  const int ly = h->geo.ly;
-  std::vector<double> both(2 * static_cast<size_t>(ly));
-  for (int y = 0; y < ly; ++y) {
-    if (!std::isfinite(rho_ref[y]) || !(rho_ref[y] > 0.0))
-      return fail(h, LBM_EINVAL, "rho_ref must be finite and > 0");
-    both[y] = rho_ref[y];
-    both[ly + y] = 1.0 / rho_ref[y];
-  }
+    return fail(h, LBM_EINVAL, "a reference state exists only for LBM_FP16DEV storage");
   DeviceGuard dg(h->device);
-  LBM_HIP(h, hipMemcpyAsync(const_cast<double*>(h->geo.ref), both.data(), ly * sizeof(double),
-                            hipMemcpyHostToDevice, h->stream));
-  LBM_HIP(h, hipMemcpyAsync(const_cast<double*>(h->geo.inv_ref), both.data() + ly, ly * sizeof(double),
-                            hipMemcpyHostToDevice, h->stream));
-  LBM_HIP(h, hipStreamSynchronize(h->stream));
-  h->has_ref = true;
+  const int rc = set_reference_table(h, rho_ref, t_lo, t_hi, y_split);
+  if (rc != LBM_OK) return rc;
   h->ready = false;  // stored deviations refer to the old reference
   return LBM_OK;
 }
 
-int lbm_get_reference(lbm_handle* h, double* rho_ref) {
+int lbm_get_reference(lbm_handle* h, double* rho_ref, double t_layers[2], int32_t* y_split) {
   if (!h) return fail(nullptr, LBM_EINVAL, "handle is NULL");
   if (!rho_ref) return fail(h, LBM_EINVAL, "rho_ref is NULL");
   if (h->geo.storage != STORAGE_F16DEV || !h->has_ref)
-    return fail(h, LBM_ESTATE, "no reference density (LBM_FP16DEV only, after init or set)");
-  DeviceGuard dg(h->device);
-  LBM_HIP(h, hipMemcpyAsync(rho_ref, h->geo.ref, h->geo.ly * sizeof(double), hipMemcpyDeviceToHost,
-                            h->stream));
-  LBM_HIP(h, hipStreamSynchronize(h->stream));
+    return fail(h, LBM_ESTATE, "no reference state (LBM_FP16DEV only, after init or set)");
+  std::copy(h->rho_ref.begin(), h->rho_ref.end(), rho_ref);
+  if (t_layers) {
+    t_layers[0] = h->t_layers[0];
+    t_layers[1] = h->t_layers[1];
+  }
+  if (y_split) *y_split = h->geo.ysplit;
   return LBM_OK;
 }
 

@@ -76,8 +76,8 @@ def load():
         "lbm_set_populations": (c_int, [H, c_void_p]),
         "lbm_get_sites": (c_int, [H, c_int32, c_void_p, c_void_p, c_void_p]),
         "lbm_get_sites_noalloc": (c_int, [H, c_int32, c_void_p, c_void_p, c_void_p]),
-        "lbm_set_reference": (c_int, [H, c_void_p]),
-        "lbm_get_reference": (c_int, [H, c_void_p]),
+        "lbm_set_reference": (c_int, [H, c_void_p, c_double, c_double, c_int32]),
+        "lbm_get_reference": (c_int, [H, c_void_p, c_void_p, c_void_p]),
         "lbm_set_timing": (c_int, [H, c_int32]),
         "lbm_read_timing": (c_int, [H, c_void_p, c_void_p]),
         "lbm_layout": (c_int, [H, c_void_p]),
@@ -217,15 +217,18 @@ def lbm_get_sites_noalloc(h, xs, ys) -> np.ndarray:
     return out
 
 
-def lbm_set_reference(h, rho_ref) -> None:
+def lbm_set_reference(h, rho_ref, t_lo: float = 1.0, t_hi: float = 1.0, y_split: int = 0) -> None:
     rho_ref = np.ascontiguousarray(rho_ref, dtype=np.float64)
-    _check(load().lbm_set_reference(h, _ptr(rho_ref)), h)
+    _check(load().lbm_set_reference(h, _ptr(rho_ref), float(t_lo), float(t_hi), int(y_split)), h)
 
 
-def lbm_get_reference(h, ly: int) -> np.ndarray:
-    out = np.empty(ly, dtype=np.float64)
-    _check(load().lbm_get_reference(h, _ptr(out)), h)
-    return out
+def lbm_get_reference(h, ly: int):
+    """(rho_ref[ly], (t_lo, t_hi), y_split) of a deviation-storage lattice."""
+    rho = np.empty(ly, dtype=np.float64)
+    t = np.empty(2, dtype=np.float64)
+    split = ctypes.c_int32(0)
+    _check(load().lbm_get_reference(h, _ptr(rho), _ptr(t), ctypes.byref(split)), h)
+    return rho, (float(t[0]), float(t[1])), int(split.value)
 
 
 def lbm_set_timing(h, enable: bool) -> None:

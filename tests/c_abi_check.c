@@ -119,8 +119,8 @@ int main(void) {
     ok &= lbm_set_populations(NULL, d) == LBM_EINVAL;
     ok &= lbm_get_sites(NULL, 1, &xy, &xy, d) == LBM_EINVAL;
     ok &= lbm_get_sites_noalloc(NULL, 1, &xy, &xy, d) == LBM_EINVAL;
-    ok &= lbm_set_reference(NULL, d) == LBM_EINVAL;
-    ok &= lbm_get_reference(NULL, d) == LBM_EINVAL;
+    ok &= lbm_set_reference(NULL, d, 1.0, 1.0, 0) == LBM_EINVAL;
+    ok &= lbm_get_reference(NULL, d, d, NULL) == LBM_EINVAL;
     ok &= lbm_set_timing(NULL, 1) == LBM_EINVAL;
     ok &= lbm_read_timing(NULL, d, cnt) == LBM_EINVAL;
     ok &= lbm_layout(NULL, lay) == LBM_EINVAL;

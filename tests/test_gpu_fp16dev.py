@@ -1,5 +1,7 @@
 """Binary16 deviation storage (binary64 arithmetic; d = (f - c)/c stored,
-c = w_l rho_ref(y)).
+c = K_l(T(y)) rho_ref(y), the zero-velocity equilibrium of a reference
+state with the density of the flat-interface Rayleigh-Taylor state per row
+and the wall temperatures as two layers split at the interface).
 
 The encoding is fixed operation by operation, so the GPU must reproduce
 the oracle's `stored(..., "fp16dev")` rule exactly for transfers,
@@ -25,16 +27,20 @@ def _gpu():
     need_gpu()
 
 
-def _ref(ns, ly):
-    _, rho = oracle.rt_fields(1, ly, ns, inputs.flat_interface(ly))
-    return rho[0].copy()
+def _state(ns, ly):
+    """Reference state (rho_ref per row, t_lo, t_hi, y_split) the library
+    builds at init: the flat-interface RT density, the wall temperatures,
+    split at the first row above the interface."""
+    flat = inputs.flat_interface(ly)
+    _, rho = oracle.rt_fields(1, ly, ns, flat)
+    return rho[0].copy(), ns.t_bottom, ns.t_top, int(np.ceil(flat.y_center))
 
 
 def _make(ns, path=lbm.LBM_PATH_FUSED, layout=lbm.LBM_LAYOUT_COLUMN):
     lat = lattice(ns, path=path, storage=lbm.LBM_FP16DEV, layout=layout)
-    ref = _ref(ns, ns.ly)
-    lbm.lbm_set_reference(lat.h, ref)
-    return lat, ref
+    state = _state(ns, ns.ly)
+    lbm.lbm_set_reference(lat.h, *state)
+    return lat, oracle.fp16dev_reference(*state)
 
 
 def _enc(f, ref):
@@ -105,13 +111,43 @@ def test_fp16dev_init_uses_flat_interface_reference():
         with pytest.raises(lbm.LbmError):
             lat.set(noisy_state(1, 37, 70))  # no reference yet
         lat.init_rt(rt)
-        ref = lbm.lbm_get_reference(lat.h, 70)
+        rho, layers, split = lbm.lbm_get_reference(lat.h, 70)
         f = lat.get()
         cons = lat.conservation()
-    assert np.max(np.abs(ref - _ref(ns, 70)) / ref) < 1e-14
+    want_rho, t_lo, t_hi, want_split = _state(ns, 70)
+    assert np.max(np.abs(rho - want_rho) / want_rho) < 1e-14
+    assert layers == (t_lo, t_hi) and split == want_split == 35
     want = oracle.init_rt(37, 70, ns, rt)
-    assert err_metric(f, want) < 2e-3
+    e = err_metric(f, want)
+    note(f"fp16dev initial state vs FP64 oracle: {e:.2e}")
+    assert e < 2e-3
     assert cons[4] == 0
+
+
+@pytest.mark.parametrize("split", [0, 1, 61, 64, 67, 100, 128, 150, 189, 192])
+def test_fp16dev_layer_boundary_anywhere(split):
+    """The fused step of a deviation lattice is the main launch over the
+    wavefronts within one temperature layer plus the band launch over the
+    (at most two) wavefronts whose rows or pull sources reach both: with
+    the layer boundary on, next to and between wavefront boundaries, and
+    at the lattice's ends, one step equals the oracle's to one binary16
+    ulp, on both layouts."""
+    lx, ly = 24, 192
+    ns = inputs.rt_config(lx, ly, t_bottom=1.08, t_top=0.93)
+    rho = _state(ns, ly)[0]
+    ref = oracle.fp16dev_reference(rho, ns.t_bottom, ns.t_top, split)
+    f = oracle.stored(noisy_state(7, lx, ly), "fp16dev", ref)
+    want = oracle.step_stored(f, ns, "fp16dev", fused=True, ref=ref)
+    dw = _enc(want, ref)
+    for layout in LAYOUTS:
+        with lattice(ns, storage=lbm.LBM_FP16DEV, layout=layout) as lat:
+            lbm.lbm_set_reference(lat.h, rho, ns.t_bottom, ns.t_top, split)
+            lat.set(f)
+            lat.step(1)
+            got = lat.get()
+        dg = _enc(got, ref).astype(np.float64)
+        ulp = np.spacing(np.abs(dw)).astype(np.float64)
+        assert np.all(np.abs(dg - dw.astype(np.float64)) <= ulp), (split, layout)
 
 
 def test_fp16dev_reference_validation():
@@ -120,15 +156,23 @@ def test_fp16dev_reference_validation():
         with pytest.raises(lbm.LbmError):
             lbm.lbm_set_reference(lat.h, np.zeros(32))
         with pytest.raises(lbm.LbmError):
+            lbm.lbm_set_reference(lat.h, np.ones(32), -1.0, 1.0, 16)
+        with pytest.raises(lbm.LbmError):
+            lbm.lbm_set_reference(lat.h, np.ones(32), 1.0, np.nan, 16)
+        with pytest.raises(lbm.LbmError):
+            lbm.lbm_set_reference(lat.h, np.ones(32), 1.0, 1.0, 33)
+        with pytest.raises(lbm.LbmError):
             lbm.lbm_get_reference(lat.h, 32)
+        lbm.lbm_set_reference(lat.h, np.linspace(0.9, 1.1, 32))  # both layers at T = 1
+        rho, layers, split = lbm.lbm_get_reference(lat.h, 32)
+        assert np.array_equal(rho, np.linspace(0.9, 1.1, 32)) and layers == (1.0, 1.0) and split == 0
     with lattice(ns) as lat:
         with pytest.raises(lbm.LbmError):
             lbm.lbm_set_reference(lat.h, np.ones(32))
 
 
-def test_fp16dev_fused_step_refreshes_halos_then_runs_one_kernel():
-    """Deviation lattices take pbc + the non-wrapping fused kernel per step
-    (the wrapping form does not fit that kernel's register bound)."""
+def test_fp16dev_fused_step_is_one_wrapping_kernel():
+    """Deviation lattices take one wrapping fused kernel per step, no pbc."""
     ns = inputs.rt_config(64, 128)
     with lattice(ns, storage=lbm.LBM_FP16DEV) as lat:
         lat.init_rt(inputs.rt_perturbation(0, 128))
@@ -136,4 +180,4 @@ def test_fp16dev_fused_step_refreshes_halos_then_runs_one_kernel():
         lat.step(3)
         ms, cnt = lbm.lbm_read_timing(lat.h)
         lbm.lbm_set_timing(lat.h, False)
-    assert cnt.tolist() == [3, 0, 0, 0, 3, 0, 0]
+    assert cnt.tolist() == [0, 0, 0, 0, 3, 0, 0]

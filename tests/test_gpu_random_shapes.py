@@ -55,15 +55,17 @@ def test_random_shape_step(case):
     i, lx, ly, path, (name, storage), layout, block = case
     ns = inputs.rt_config(lx, ly, tau=0.6 + 0.05 * (i % 8), gravity=1e-4 * (1 + i % 3),
                           t_bottom=1.0 + 0.01 * (i % 7), t_top=1.0 - 0.01 * (i % 5))
-    ref = None
+    ref = rows = None
     f = noisy_state(i, lx, ly)
     if name == "fp16dev":
-        _, rho = oracle.rt_fields(1, ly, ns, inputs.flat_interface(ly))
-        ref = rho[0].copy()
+        flat = inputs.flat_interface(ly)
+        _, rho = oracle.rt_fields(1, ly, ns, flat)
+        rows = (rho[0].copy(), ns.t_bottom, ns.t_top, int(np.ceil(flat.y_center)))
+        ref = oracle.fp16dev_reference(*rows)
     f = oracle.stored(f, name, ref)
     with lattice(ns, path=path, storage=storage, layout=layout, block=block) as lat:
-        if ref is not None:
-            lbm.lbm_set_reference(lat.h, ref)
+        if rows is not None:
+            lbm.lbm_set_reference(lat.h, *rows)
         lat.set(f)
         lat.step(1)
         got = lat.get()
@@ -79,8 +81,8 @@ def test_random_shape_step(case):
         note(f"case {case}: {u} ulp")
         assert u <= 1
     with lattice(ns, path=lbm.LBM_PATH_SEPARATE, storage=storage, layout=layout, block=block) as lat:
-        if ref is not None:
-            lbm.lbm_set_reference(lat.h, ref)
+        if rows is not None:
+            lbm.lbm_set_reference(lat.h, *rows)
         lat.set(f)
         lat.step(4)
         sep = lat.get()

@@ -190,11 +190,10 @@ def test_fp16dev_encoding_properties():
     decodes exactly; a value c (1 + d) with d a binary16 number round-trips
     bit for bit; and the decoded value is within half a binary16 ulp of d
     (relative to c) of the original."""
-    k = oracle.constants()
     ly = 16
-    ref = np.linspace(0.7, 1.4, ly)
-    c = k.w[:, None, None] * ref[None, None, :]
-    c3 = np.broadcast_to(c, (37, 2, ly)).copy()
+    ref = oracle.fp16dev_reference(np.linspace(0.7, 1.4, ly), 1.07, 0.94, 9)
+    c = ref[0]
+    c3 = np.broadcast_to(c[:, None, :], (37, 2, ly)).copy()
     assert np.all(oracle.encode_fp16dev(c3, ref) == 0)
     assert np.array_equal(oracle.decode_fp16dev(oracle.encode_fp16dev(c3, ref), ref), c3)
     d = inputs.noise(3, (37, 2, ly), 0.2).astype(np.float16)
@@ -205,3 +204,36 @@ def test_fp16dev_encoding_properties():
     dev = (g - c3) / c3
     tol = np.spacing(np.abs(dev).astype(np.float16)).astype(np.float64) * 0.5 * (1 + 2.0 ** -12) + 1e-12
     assert np.all(np.abs((back - g) / c3) <= tol)
+
+
+def test_fp16dev_reference_is_the_rest_equilibrium_of_two_layers():
+    """The reference c_l(y) = K_l(T(y)) rho_ref(y) is the zero-velocity
+    equilibrium of the reference state: it equals the Hermite equilibrium
+    of reading R3 at (rho_ref(y), u = 0, T(y)) to rounding, with T the
+    lower layer's temperature below y_split and the upper one's from it up.
+    Far from the interface the flat-interface Rayleigh-Taylor state is at
+    its row's reference (|d| < 1e-3 there), where a reference w_l rho_ref
+    leaves the temperature part of the equilibrium, up to 0.3 of c for the
+    outer shells at T = 1.05, in d.  With both layers at 1 the reference is
+    w_l rho_ref exactly, and the encoding factor is the product of the
+    rounded reciprocals."""
+    k = oracle.constants()
+    ly = 64
+    cfg = inputs.rt_config(8, ly)
+    flat = inputs.flat_interface(ly)
+    T, rho = oracle.rt_fields(1, ly, cfg, flat)
+    split = int(np.ceil(flat.y_center))
+    c, inv = oracle.fp16dev_reference(rho[0], cfg.t_bottom, cfg.t_top, split)
+    zero = np.zeros(ly)
+    t_layer = np.where(np.arange(ly) < split, cfg.t_bottom, cfg.t_top)
+    feq = oracle.equilibrium(rho[0], zero, zero, t_layer)
+    assert np.max(np.abs(feq - c) / c) < 1e-14
+    f = oracle.init_rt(8, ly, cfg, flat)
+    d = oracle.encode_fp16dev(f, (c, inv)).astype(np.float64)
+    far = np.abs(np.arange(ly) - flat.y_center) > 12
+    assert np.max(np.abs(d[:, :, far])) < 1e-3
+    old = k.w[:, None] * rho[0][None, :]
+    assert np.max(np.abs((f[:, 0, far] - old[:, far]) / old[:, far])) > 0.25
+    c1, inv1 = oracle.fp16dev_reference(rho[0], 1.0, 1.0, split)
+    assert np.array_equal(c1, old)
+    assert np.array_equal(inv1, (1.0 / k.w)[:, None] * (1.0 / rho[0])[None, :])
