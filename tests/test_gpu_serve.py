@@ -6,8 +6,10 @@ budget admits them, so requests queue, lattices join the engine while
 others are mid-run, finish at different steps, leave, and free slots and
 memory for the queue.  Every request's final populations must be
 bit-identical to the same request stepped alone with lbm_step (the engine
-runs the fused kernel's arithmetic per lattice), and one FP64 request is
-checked against the oracle.
+runs the fused kernel's arithmetic per lattice), under both policies (the
+default one, which also takes unfinished lattices off the engine and puts
+them back later, and processor sharing), and one FP64 request is checked
+against the oracle.
 """
 import numpy as np
 import pytest
@@ -45,32 +47,41 @@ def _alone(srv, r):
         return lat.get()
 
 
-def test_served_results_equal_each_request_alone():
+@pytest.mark.parametrize("policy,fill", [("srpt", 6000), ("ps", 0)])
+def test_served_results_equal_each_request_alone(policy, fill):
     reqs = _requests()
     # room for about three of these lattices at once: the rest queue
     sizes = sorted(lbm.lbm_required_bytes(lbm.config_from(
         inputs.rt_config(r.lx, r.ly), storage=lbm.LBM_FP32 if r.storage else lbm.LBM_FP64)) for r in reqs)
     budget = sum(sizes[-3:])
-    note(f"serving {len(reqs)} requests, budget {budget} bytes, 4 slots, chunk 3")
-    srv = Server(lbm, inputs, budget, max_slots=4, chunk=3, keep=[r.rid for r in reqs])
+    note(f"serving {len(reqs)} requests ({policy}), budget {budget} bytes, 4 slots, chunk 3")
+    srv = Server(lbm, inputs, budget, max_slots=4, chunk=3, keep=[r.rid for r in reqs],
+                 policy=policy, fill_sites=fill)
     done, makespan, site_steps = srv.run(reqs)
     assert sorted(done) == [r.rid for r in reqs]
     assert site_steps == sum(r.lx * r.ly * r.steps for r in reqs)
 
-    # continuous batching happened: several lattices active at once, a
-    # request admitted while others were mid-run after one had retired,
-    # and a freed slot reused
-    active, peak, joined_after_leave, retired_slots, reused = set(), 0, False, set(), False
+    # continuous batching happened: several lattices on the engine at once,
+    # a lattice joining while others were mid-run after one had left, and a
+    # freed slot reused; under srpt, lattices also left the engine
+    # unfinished and rejoined later
+    on, peak, joined_after_leave, left_slots, reused = set(), 0, False, set(), False
+    paused, resumed = set(), set()
     for _, kind, rid, slot in srv.events:
-        if kind == "admit":
-            joined_after_leave |= bool(retired_slots) and bool(active)
-            reused |= slot in retired_slots
-            active.add(rid)
-            peak = max(peak, len(active))
-        else:
-            active.discard(rid)
-            retired_slots.add(slot)
+        if kind == "join":
+            joined_after_leave |= bool(left_slots) and bool(on)
+            reused |= slot in left_slots
+            resumed |= {rid} & paused
+            on.add(rid)
+            peak = max(peak, len(on))
+        elif kind in ("leave", "retire"):
+            on.discard(rid)
+            left_slots.add(slot)
+            if kind == "leave":
+                paused.add(rid)
     assert peak >= 2 and joined_after_leave and reused
+    if policy == "srpt":
+        assert resumed
 
     mismatches = [r.rid for r in reqs if not np.array_equal(srv.kept[r.rid], _alone(srv, r))]
     assert mismatches == []

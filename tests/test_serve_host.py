@@ -8,6 +8,7 @@ bookkeeping are exercised without a GPU.
 import types
 
 import numpy as np
+import pytest
 
 from paper_1703_00185_amd import inputs, serve
 
@@ -49,7 +50,7 @@ class FakeEngine:
         return self.left
 
     def remove(self, slot):
-        assert self.left[slot] == 0
+        FakeEngine.log.append(("remove", slot, self.left[slot]))
         del self.left[slot]
 
     def set_tiling(self, *a):
@@ -73,7 +74,8 @@ def fake_lbm(budget_log):
     return m
 
 
-def test_admission_budget_fifo_and_completion():
+@pytest.mark.parametrize("policy", ["srpt", "ps"])
+def test_admission_budget_fifo_and_completion(policy):
     FakeEngine.log = []
     lbm = fake_lbm([])
     drawn = serve.draw_requests(3, 40)
@@ -81,7 +83,7 @@ def test_admission_budget_fifo_and_completion():
             for i, (lx, ly, st, sto, seed) in enumerate(drawn)]
     budget = 3 * max(lbm.lbm_required_bytes(lbm.config_from(inputs.rt_config(r.lx, r.ly), r.storage))
                      for r in reqs)
-    srv = serve.Server(lbm, inputs, budget, max_slots=8, chunk=5)
+    srv = serve.Server(lbm, inputs, budget, max_slots=8, chunk=5, policy=policy)
     orig_config = srv.config
 
     def tagged(r):
@@ -104,7 +106,7 @@ def test_admission_budget_fifo_and_completion():
         FakeEngine.add = orig_add
     assert sorted(done) == list(range(40))
     assert peak[0] <= budget
-    admitted = [rid for kind, rid in FakeEngine.log if kind == "add"]
+    admitted = [rid for _, kind, rid, _ in srv.events if kind == "admit"]
     assert admitted == sorted(admitted)          # first come, first served
     assert srv.used == 0
     assert site_steps == sum(r.lx * r.ly * r.steps for r in reqs)
@@ -137,3 +139,54 @@ def test_request_distribution():
     # log-uniform sites: the median of log(sites) sits mid-range
     ls = np.log(lx * ly)
     assert abs(np.median(ls) - 0.5 * (np.log(64 * 128) + np.log(1024 * 4096))) < 0.3
+
+
+def test_one_at_a_time_baseline_runs_in_arrival_order_after_arrival():
+    """The measured baseline serves one request at a time, FIFO, each
+    started no earlier than its arrival; FP64 storage for every request."""
+    ran = []
+
+    class TimedLattice(FakeLattice):
+        def step(self, n):
+            ran.append((n, self.cfg.storage))
+
+    m = fake_lbm([])
+    m.Lattice = TimedLattice
+    reqs = [serve.Request(rid=i, arrival=a, lx=8, ly=16, steps=10 + i, storage=i % 2, seed=i)
+            for i, a in enumerate([0.0, 0.05, 0.02, 0.3])]
+    lat, busy = serve.run_one_at_a_time(m, inputs, reqs, sync=lambda: None)
+    assert [n for n, _ in ran] == [10, 12, 11, 13]      # arrival order
+    assert all(storage == 0 for _, storage in ran)      # plain FP64
+    assert len(lat) == 4 and all(x >= 0.0 for x in lat)
+    assert 0.0 <= busy < 0.3
+
+
+def test_srpt_steps_least_remaining_work_first_up_to_fill():
+    """The engine set is the resident lattices with the least remaining work
+    (sites x steps left), taken until the fill size is reached; the others
+    wait resident, and every lattice ends with its own step count."""
+    FakeEngine.log = []
+    lbm = fake_lbm([])
+    reqs = [serve.Request(0, 0.0, 64, 128, 50, 0, 1),    # 409,600 site-steps
+            serve.Request(1, 0.0, 64, 128, 10, 1, 2),    # 81,920
+            serve.Request(2, 0.0, 128, 256, 4, 0, 3)]    # 131,072
+    srv = serve.Server(lbm, inputs, 1 << 40, max_slots=4, chunk=100, fill_sites=2 * 64 * 128)
+    steps_run = []
+    orig_step = FakeEngine.step
+
+    def step(self, n):
+        steps_run.append((n, sorted(self.left)))
+        orig_step(self, n)
+
+    FakeEngine.step = step
+    try:
+        done, _, site_steps = srv.run(reqs)
+    finally:
+        FakeEngine.step = orig_step
+    assert sorted(done) == [0, 1, 2]
+    joins = [rid for _, kind, rid, _ in srv.events if kind == "join"]
+    # 1 (least work) and 2 fill the engine first; 0 waits until one retires
+    assert joins[:2] == [1, 2] and 0 in joins[2:]
+    order = [rid for _, kind, rid, _ in srv.events if kind == "retire"]
+    assert order == [2, 1, 0]
+    assert site_steps == sum(r.lx * r.ly * r.steps for r in reqs)
