@@ -87,10 +87,11 @@ def test_full_size_step_at_sampled_sites():
 
 
 def _stored_at_sites(g, storage, ref_rows, ys):
-    """oracle.stored() of populations g[37, n] at sites with rows ys."""
+    """oracle.stored() of populations g[37, n] at sites with rows ys
+    (ref_rows: the deviation reference of oracle.fp16dev_reference)."""
     if storage == "fp32":
         return oracle.stored(g, "fp32")
-    return oracle.stored(g[:, None, :], "fp16dev", ref_rows[ys])[:, 0, :]
+    return oracle.stored(g[:, None, :], "fp16dev", (ref_rows[0][:, ys], ref_rows[1][:, ys]))[:, 0, :]
 
 
 def _ulps_apart(got, want, storage, ref_rows, ys):
@@ -98,7 +99,7 @@ def _ulps_apart(got, want, storage, ref_rows, ys):
     if storage == "fp32":
         a, b = got.astype(np.float32), want.astype(np.float32)
         return float(np.max(np.abs(a.view(np.int32).astype(np.int64) - b.view(np.int32).astype(np.int64))))
-    r = ref_rows[ys]
+    r = (ref_rows[0][:, ys], ref_rows[1][:, ys])
     da = oracle.encode_fp16dev(got[:, None, :], r)[:, 0, :].astype(np.float64)
     db = oracle.encode_fp16dev(want[:, None, :], r)[:, 0, :]
     return float(np.max(np.abs(da - db.astype(np.float64)) / np.spacing(np.abs(db)).astype(np.float64)))
@@ -120,8 +121,9 @@ def test_full_size_reduced_storage_step_at_sampled_sites(storage):
     code = lbm.LBM_FP32 if storage == "fp32" else lbm.LBM_FP16DEV
     ref_rows = None
     if storage == "fp16dev":
-        _, rho = oracle.rt_fields(1, LY, ns, inputs.flat_interface(LY))
-        ref_rows = rho[0].copy()
+        flat = inputs.flat_interface(LY)
+        _, rho = oracle.rt_fields(1, LY, ns, flat)
+        ref_rows = oracle.fp16dev_reference(rho[0], ns.t_bottom, ns.t_top, int(np.ceil(flat.y_center)))
     note(f"oracle initial state on sampled columns ({storage})")
     f0 = _oracle_initial_state(ns, rt, xs)
     cols = np.unique(((xs[:, None] + np.arange(-3, 4)[None, :]) % LX).ravel())
@@ -143,3 +145,26 @@ def test_full_size_reduced_storage_step_at_sampled_sites(storage):
     assert u_init <= 1
     assert u_step <= 2
     assert cons[4] == 0
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("storage", [lbm.LBM_FP64, lbm.LBM_FP16DEV])
+def test_full_size_planar_equals_column_layout(storage):
+    """At 2048 x 8192 the planar layout (population planes 37 x 16.8 M
+    elements apart, element offsets past 2^32 bytes) and the benchmark's
+    column layout give the same bits after three fused steps: at the
+    sampled sites and in the conservation sums, which read every site in a
+    fixed order."""
+    ns = inputs.rt_config(LX, LY)
+    rt = inputs.rt_perturbation(1, LY)
+    xs, ys = _samples()
+    out = {}
+    for layout in (lbm.LBM_LAYOUT_COLUMN, lbm.LBM_LAYOUT_PLANAR):
+        with lattice(ns, path=lbm.LBM_PATH_FUSED, layout=layout, storage=storage) as lat:
+            lat.init_rt(rt)
+            lat.step(3)
+            out[layout] = (lat.sites(xs, ys), lat.conservation())
+    col, pla = out[lbm.LBM_LAYOUT_COLUMN], out[lbm.LBM_LAYOUT_PLANAR]
+    assert np.array_equal(col[0], pla[0])
+    assert np.array_equal(col[1], pla[1])
+    assert col[1][4] == 0
