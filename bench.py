@@ -144,15 +144,25 @@ def field_errors(ref, got) -> dict:
 
 
 def cpu_model() -> str:
+    """The host CPU as /proc/cpuinfo names it: model name, with the family,
+    model and stepping numbers (some hosts report only a brand name)."""
+    fields = {}
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if ":" not in line:
+                    if fields:
+                        break       # end of the first processor's block
+                    continue
+                k, v = (t.strip() for t in line.split(":", 1))
+                fields.setdefault(k, v)
     except OSError:
         pass
-    import platform
-    return platform.processor() or "unknown"
+    if "model name" not in fields:
+        import platform
+        return platform.processor() or "unknown"
+    ids = ", ".join(f"{k} {fields[k]}" for k in ("cpu family", "model", "stepping") if k in fields)
+    return f"{fields['model name']} ({ids})" if ids else fields["model name"]
 
 
 def single_kernel(name: str, run: dict, steps: int) -> dict:
@@ -368,13 +378,12 @@ def main() -> int:
     reduced = {}
     for name, storage, eb in (("fp32", lbm.LBM_FP32, 4), ("fp16dev", lbm.LBM_FP16DEV, 2)):
         log(f"fused path, {name} storage {lx}x{ly}: {args.warmup} warmup + {args.steps} timed steps")
-        # binary16 deviations launch pbc before the fused kernel: per-launch breakdown
+        # one fused launch per step for every storage type
         r3 = time_path(lbm, ns, rt, lbm.LBM_PATH_FUSED, args.steps, args.warmup,
-                       dict(extra, storage=storage),
-                       breakdown_steps=breakdown if storage == lbm.LBM_FP16DEV else 0, fields=True)
+                       dict(extra, storage=storage), fields=True)
         errors = field_errors(fp64_fields, r3.pop("moments"))
         w3 = r3["wall"]
-        k3 = r3["kernels"] if storage == lbm.LBM_FP16DEV else single_kernel("fused", r3, args.steps)
+        k3 = single_kernel("fused", r3, args.steps)
         k3 = kernel_bandwidth(k3, sites, lx, ly, elem_bytes=eb)
         reduced[name] = {"mlups": sites * args.steps / w3 / 1e6, "ms_per_step": w3 / args.steps * 1e3,
                          "speedup_vs_fp64": wall / w3, "bytes_per_site": 2 * 37 * eb,
