@@ -78,8 +78,10 @@ typedef enum {
   LBM_PATH_SEPARATE = 0, /* pbc, propagate, bc, collide: four kernels */
   LBM_PATH_FUSED = 1,    /* one kernel doing propagate+bc+collide, periodic
                             x by wrapping the source column (no pbc launch,
-                            halo columns unused); LBM_FP16DEV lattices run
-                            pbc, then the kernel reading the halo columns */
+                            halo columns unused); LBM_FP16DEV lattices whose
+                            reference layer boundary lies inside the lattice
+                            add a small launch over the (at most two)
+                            wavefronts per column that straddle it */
   LBM_PATH_REGIONS = 2   /* region split (Sec. 5, 1-D tiling): the fused
                             kernel on the bulk columns 3..Lx-4 runs on the
                             bound stream while a second stream refreshes
@@ -112,9 +114,7 @@ typedef enum {
   LBM_PHASE_BC = 2,        /* thermal walls on the 6 wall rows (in place) */
   LBM_PHASE_COLLIDE = 3,   /* collision into the other buffer */
   LBM_PHASE_FUSED = 4,     /* propagate + bc + collide into the other buffer,
-                              periodic x by wrapping (reads no halo); for
-                              LBM_FP16DEV it reads the halo columns (run
-                              PBC first) */
+                              periodic x by wrapping (reads no halo) */
   LBM_PHASE_FUSED_BULK = 5,   /* timing only: region path, bulk columns */
   LBM_PHASE_FUSED_BORDER = 6, /* timing only: region path, border columns */
   LBM_NPHASES = 7

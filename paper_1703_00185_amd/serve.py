@@ -245,11 +245,14 @@ def fifo_latencies(arrivals, service):
 def serve_workload(lbm, inputs, requests: int = 5000, seed: int = 0, load: float = 0.8,
                    budget_gb: float = 200.0, max_slots: int = 1024, chunk: int = 25,
                    check: int = 12, log=None, measure_baseline: bool = True,
-                   policy: str = "srpt") -> dict:
+                   policy: str = "srpt", rate: float | None = None, serve: bool = True) -> dict:
     """Run the serving workload on the current GPU; returns the result
     record (the JSON object main() prints).  With measure_baseline the
     one-request-at-a-time FP64 server is also run on the GPU under the same
-    arrivals (as long again as the served run)."""
+    arrivals (as long again as the served run).  rate fixes the arrival
+    rate (requests per second) instead of load x the measured capacity, so
+    that two runs can share their arrivals; serve=False runs only the
+    baselines."""
     log = log or (lambda msg: print(msg, file=sys.stderr, flush=True))
     drawn = draw_requests(seed, requests)
     work = np.array([lx * ly * st for lx, ly, st, _, _ in drawn], dtype=np.float64)
@@ -275,7 +278,8 @@ def serve_workload(lbm, inputs, requests: int = 5000, seed: int = 0, load: float
     for lat in cal_lats:
         lat.close()
     capacity = cal_mlups * 1e6 / float(work.mean())       # requests per second
-    rate = load * capacity
+    if rate is None:
+        rate = load * capacity
     arrivals = poisson_arrivals(seed, requests, rate)
     reqs = [Request(i, float(arrivals[i]), lx, ly, st, sto, s)
             for i, (lx, ly, st, sto, s) in enumerate(drawn)]
@@ -283,28 +287,37 @@ def serve_workload(lbm, inputs, requests: int = 5000, seed: int = 0, load: float
         f"arrival rate {rate:.2f} req/s, {requests} requests, "
         f"{work.sum() / 1e12:.2f} T site-updates")
 
-    rng = np.random.default_rng(seed + 7)
-    small = [r.rid for r in reqs if r.lx * r.ly <= 65536]
-    keep = set(rng.choice(small, size=min(check, len(small)), replace=False).tolist()) if small else set()
-    srv = Server(lbm, inputs, int(budget_gb * 2**30), max_slots, chunk, keep, policy=policy)
-    srv.engine.set_tiling(block, groups, sched)
-    done, makespan, site_steps = srv.run(reqs)
-    lat_served = [done[r.rid] - r.arrival for r in reqs]
-    mlups = site_steps / makespan / 1e6
-    busy_mlups = site_steps / max(srv.busy, 1e-9) / 1e6
-    log(f"[serve] served {len(done)} requests in {makespan:.1f} s: {mlups:.0f} MLUPS "
-        f"({busy_mlups:.0f} over busy time), p50 {percentile(lat_served, 50):.2f} s, "
-        f"p99 {percentile(lat_served, 99):.2f} s")
+    served, identical, fill = None, None, None
+    if serve:
+        rng = np.random.default_rng(seed + 7)
+        small = [r.rid for r in reqs if r.lx * r.ly <= 65536]
+        keep = set(rng.choice(small, size=min(check, len(small)), replace=False).tolist()) if small else set()
+        srv = Server(lbm, inputs, int(budget_gb * 2**30), max_slots, chunk, keep, policy=policy)
+        srv.engine.set_tiling(block, groups, sched)
+        fill = srv.fill_sites
+        done, makespan, site_steps = srv.run(reqs)
+        lat_served = [done[r.rid] - r.arrival for r in reqs]
+        mlups = site_steps / makespan / 1e6
+        busy_mlups = site_steps / max(srv.busy, 1e-9) / 1e6
+        log(f"[serve] served {len(done)} requests in {makespan:.1f} s: {mlups:.0f} MLUPS "
+            f"({busy_mlups:.0f} over busy time), p50 {percentile(lat_served, 50):.2f} s, "
+            f"p99 {percentile(lat_served, 99):.2f} s")
+        served = {"mlups": mlups, "mlups_busy": busy_mlups, "busy_s": srv.busy,
+                  "makespan_s": makespan,
+                  "latency_p50_s": percentile(lat_served, 50),
+                  "latency_p99_s": percentile(lat_served, 99),
+                  "latency_mean_s": float(np.mean(lat_served))}
 
-    # identical alone and in the mix
-    mismatches = 0
-    for rid in sorted(srv.kept):
-        r = reqs[rid]
-        lat = lbm.Lattice(srv.config(r))
-        lat.init_rt(inputs.rt_perturbation(r.seed, r.ly))
-        lat.step(r.steps)
-        mismatches += int(not np.array_equal(lat.get(), srv.kept[rid]))
-        lat.close()
+        # identical alone and in the mix
+        mismatches = 0
+        for rid in sorted(srv.kept):
+            r = reqs[rid]
+            lat = lbm.Lattice(srv.config(r))
+            lat.init_rt(inputs.rt_perturbation(r.seed, r.ly))
+            lat.step(r.steps)
+            mismatches += int(not np.array_equal(lat.get(), srv.kept[rid]))
+            lat.close()
+        identical = {"checked": len(srv.kept), "mismatches": mismatches}
 
     # one request at a time, plain FP64, same arrivals
     grid = sorted({(64 * 2 ** k, 128 * 2 ** k) for k in range(5)} |
@@ -339,14 +352,10 @@ def serve_workload(lbm, inputs, requests: int = 5000, seed: int = 0, load: float
     return {
         "workload": f"{requests} Rayleigh-Taylor requests, 64x128..1024x4096 log-uniform, "
                     f"100-5000 steps, FP64/FP32 50/50, Poisson arrivals at {load} of capacity",
-        "policy": {"name": policy, "fill_sites": srv.fill_sites, "chunk_steps": chunk},
+        "policy": {"name": policy, "fill_sites": fill, "chunk_steps": chunk},
         "arrival_rate_per_s": rate, "capacity_per_s": capacity, "calibration_mlups": cal_mlups,
         "tiling": {"block": block, "groups": groups, "schedule": sched},
-        "served": {"mlups": mlups, "mlups_busy": busy_mlups, "busy_s": srv.busy,
-                   "makespan_s": makespan,
-                   "latency_p50_s": percentile(lat_served, 50),
-                   "latency_p99_s": percentile(lat_served, 99),
-                   "latency_mean_s": float(np.mean(lat_served))},
+        "served": served,
         "one_at_a_time_fp64": {"latency_p50_s": base["latency_p50_s"],
                                "latency_p99_s": base["latency_p99_s"],
                                "measured": measured,
@@ -358,7 +367,7 @@ def serve_workload(lbm, inputs, requests: int = 5000, seed: int = 0, load: float
                                                               for k, v in rates.items()},
                                    "note": "FIFO single server, service times from measured "
                                            "FP64 rates per lattice size"}},
-        "identical_alone_and_in_mix": {"checked": len(srv.kept), "mismatches": mismatches},
+        "identical_alone_and_in_mix": identical,
     }
 
 
@@ -375,6 +384,10 @@ def main() -> int:
                     help="which resident lattices the engine steps (see Server)")
     ap.add_argument("--no-measured-baseline", action="store_true",
                     help="only simulate the one-at-a-time FP64 server (it takes as long as serving)")
+    ap.add_argument("--rate", type=float, default=None,
+                    help="arrival rate in requests/s (default: --load x the measured capacity)")
+    ap.add_argument("--baseline-only", action="store_true",
+                    help="run only the one-at-a-time FP64 servers (with --rate, on another run's arrivals)")
     args = ap.parse_args()
 
     import torch
@@ -385,9 +398,11 @@ def main() -> int:
 
     out = serve_workload(lbm, inputs, args.requests, args.seed, args.load, args.budget_gb,
                          args.max_slots, args.chunk, args.check,
-                         measure_baseline=not args.no_measured_baseline, policy=args.policy)
+                         measure_baseline=not args.no_measured_baseline, policy=args.policy,
+                         rate=args.rate, serve=not args.baseline_only)
     print(json.dumps(out), flush=True)
-    return 0 if out["identical_alone_and_in_mix"]["mismatches"] == 0 else 1
+    ident = out["identical_alone_and_in_mix"]
+    return 0 if ident is None or ident["mismatches"] == 0 else 1
 
 
 if __name__ == "__main__":
