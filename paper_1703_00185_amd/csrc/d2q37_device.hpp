@@ -61,6 +61,37 @@ __device__ __forceinline__ S ld(const S* base, unsigned byte_off) {
   }
 }
 
+// Element at voff + soff bytes from the base of descriptor r: voff per
+// lane, soff wavefront-uniform (a scalar register operand of the buffer
+// instruction), so one descriptor serves every run of a column and each
+// access costs one scalar add instead of a 64-bit base and a descriptor.
+// The caller keeps soff + voff below the descriptor's range.
+template <class S>
+__device__ __forceinline__ S ld_at(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(S) == 2) {
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+  } else if constexpr (sizeof(S) == 4) {
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  } else {
+    static_assert(sizeof(S) == 8, "2-, 4- or 8-byte elements");
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  }
+}
+
+// Non-temporal store at voff + soff bytes from the base of descriptor r.
+template <class S>
+__device__ __forceinline__ void st_nt_at(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, S v) {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  if constexpr (sizeof(S) == 2) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, soff, kNonTemporal);
+  } else if constexpr (sizeof(S) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, kNonTemporal);
+  } else {
+    static_assert(sizeof(S) == 8, "2-, 4- or 8-byte elements");
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, kNonTemporal);
+  }
+}
+
 // Non-temporal store (streaming: no reuse expected from the caches).
 template <class S>
 __device__ __forceinline__ void st_nt(S* base, unsigned byte_off, S v) {

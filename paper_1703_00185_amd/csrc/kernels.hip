@@ -70,18 +70,38 @@ __device__ __forceinline__ int source_column(const Geometry& g, int x, int ex) {
 // Pull gather of Eq. (10): f_l(x, y) <- f_l(x - e_lx, y - e_ly), periodic
 // in x.  Interior form, for a column x uniform over the work-group: the 37
 // source runs start at uniform (scalar) addresses and all loads share the
-// lane's byte offset.
-template <bool WRAP, class C>
+// lane's byte offset.  RUN_OFF: one buffer descriptor per source column
+// (7), based 3 rows before the column's first run, and the run of
+// population l addressed by the scalar offset l * pstride + 3 - e_ly
+// elements (the caller guarantees that a column's runs span less than
+// 2^31 bytes); else one descriptor per population.
+template <bool WRAP, bool RUN_OFF = false, class C>
 __device__ __forceinline__ void gather_interior(const Geometry& g, const C& cd,
                                                 const typename C::S* __restrict__ src, int x, int y,
                                                 double (&f)[NPOP]) {
   using S = typename C::S;
   const unsigned off = static_cast<unsigned>(y) * static_cast<unsigned>(sizeof(S));
+  if constexpr (RUN_OFF) {
+    constexpr int kReachY = HALO;              // max |e_y| (the velocity set is symmetric)
+    __amdgpu_buffer_rsrc_t col[2 * HALO + 1];  // source column x - e_x, e_x = -3 .. 3
 #pragma unroll
-  for (int l = 0; l < NPOP; ++l) {
-    const S* base = src + (static_cast<long long>(source_column<WRAP>(g, x, EX[l])) * g.cstride +
-                           static_cast<long long>(l) * g.pstride - EY[l]);
-    f[l] = cd.dec(ld(base, off), l, y - EY[l]);
+    for (int e = -HALO; e <= HALO; ++e)
+      col[e + HALO] =
+          buffer_at(src + (static_cast<long long>(source_column<WRAP>(g, x, e)) * g.cstride - kReachY));
+    const unsigned ps = static_cast<unsigned>(g.pstride) * static_cast<unsigned>(sizeof(S));
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) {
+      const unsigned so =
+          static_cast<unsigned>(l) * ps + static_cast<unsigned>((kReachY - EY[l]) * static_cast<int>(sizeof(S)));
+      f[l] = cd.dec(ld_at<S>(col[EX[l] + HALO], off, so), l, y - EY[l]);
+    }
+  } else {
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) {
+      const S* base = src + (static_cast<long long>(source_column<WRAP>(g, x, EX[l])) * g.cstride +
+                             static_cast<long long>(l) * g.pstride - EY[l]);
+      f[l] = cd.dec(ld(base, off), l, y - EY[l]);
+    }
   }
 }
 
@@ -116,16 +136,24 @@ __device__ __forceinline__ void load_column_site(const Geometry& g, const C& cd,
 
 // Store of site (x, y), x uniform over the work-group.  Non-temporal: the
 // step kernels write every element once and nothing reads it back before
-// the next launch.
-template <class C>
+// the next launch.  RUN_OFF: one descriptor for the column and scalar run
+// offsets, as in gather_interior.
+template <bool RUN_OFF = false, class C>
 __device__ __forceinline__ void store_column_site(const Geometry& g, const C& cd,
                                                   typename C::S* __restrict__ dst, int x, int y,
                                                   const double (&f)[NPOP]) {
   using S = typename C::S;
   const unsigned off = static_cast<unsigned>(y) * static_cast<unsigned>(sizeof(S));
   S* col = dst + static_cast<long long>(x + HALO) * g.cstride;
+  if constexpr (RUN_OFF) {
+    const __amdgpu_buffer_rsrc_t r = buffer_at(col);
+    const unsigned ps = static_cast<unsigned>(g.pstride) * static_cast<unsigned>(sizeof(S));
 #pragma unroll
-  for (int l = 0; l < NPOP; ++l) st_nt(col + static_cast<long long>(l) * g.pstride, off, cd.enc(f[l], l, y));
+    for (int l = 0; l < NPOP; ++l) st_nt_at<S>(r, off, static_cast<unsigned>(l) * ps, cd.enc(f[l], l, y));
+  } else {
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) st_nt(col + static_cast<long long>(l) * g.pstride, off, cd.enc(f[l], l, y));
+  }
 }
 
 // Any site (x per lane).
@@ -242,7 +270,7 @@ __global__ void __launch_bounds__(BLOCK) collide_kernel(const typename C::S* __r
 }
 
 // One site of the fused step (below), with the codec cd.
-template <class C, int BLOCK, bool WRAP, bool BAND>
+template <class C, int BLOCK, bool WRAP, bool BAND, bool RUN_OFF>
 __device__ __forceinline__ void fused_site(const Geometry& g, const C& cd, const typename C::S* __restrict__ src,
                                            typename C::S* __restrict__ dst, const CollideParams& c,
                                            const WallParams& w, const ColumnSet& cols, int x, int y,
@@ -273,14 +301,14 @@ __device__ __forceinline__ void fused_site(const Geometry& g, const C& cd, const
     const ConstD* kf = (ConstD*)(g.kf);
     const CodecF16DevLayer lc{g.ref, g.inv_ref, kf + (hi ? KF_HI : KF_LO), kf + (hi ? KF_INV_HI : KF_INV_LO)};
     if (interior_wave(g, ywave)) {
-      gather_interior<WRAP>(g, lc, src, x, y, f);
+      gather_interior<WRAP, RUN_OFF>(g, lc, src, x, y, f);
     } else {
       const int yc = y < g.ly ? y : g.ly - 1;
       gather_wall<WRAP>(g, lc, src, x, yc, f);
       if (yc < WALL_ROWS || yc >= g.ly - WALL_ROWS) thermalise(f, yc < WALL_ROWS, w);
     }
     collide_site(f, c);
-    if (y < g.ly) store_column_site(g, lc, dst, x, y, f);
+    if (y < g.ly) store_column_site<RUN_OFF>(g, lc, dst, x, y, f);
     return;
   }
   if constexpr (C::kWrapAlways) {
@@ -320,14 +348,19 @@ __device__ __forceinline__ void fused_site(const Geometry& g, const C& cd, const
 // BAND: the launch over the wavefronts that straddle the layers of the
 // binary16 deviation reference (see fused_site); a few wavefronts per
 // column, so it takes no register bound.
-template <class C, int BLOCK, bool WRAP, bool BAND = false>
+// RUN_OFF: scalar run offsets in the interior gather and the store (one
+// buffer descriptor per column); the launcher takes it for binary16
+// deviation lattices whose column runs span less than 2^31 bytes, where
+// it removes most of the scalar address arithmetic that otherwise
+// precedes each of the 74 accesses.
+template <class C, int BLOCK, bool WRAP, bool BAND = false, bool RUN_OFF = false>
 __global__ void __launch_bounds__(BLOCK, BAND ? 1 : C::kMinWaves) fused_kernel(const typename C::S* __restrict__ src,
                                                       typename C::S* __restrict__ dst, Geometry g,
                                                       CollideParams c, WallParams w, ColumnSet cols) {
   int x, y, ywave;
   lane_site<BLOCK>(g, cols, x, y, ywave);
   const C cd = C::of(g);
-  fused_site<C, BLOCK, WRAP, BAND>(g, cd, src, dst, c, w, cols, x, y, ywave);
+  fused_site<C, BLOCK, WRAP, BAND, RUN_OFF>(g, cd, src, dst, c, w, cols, x, y, ywave);
 }
 
 // Per-site rho, ux, uy, T into out[4][lx][ly] (Sec. 2 moment definitions;
@@ -671,13 +704,24 @@ hipError_t launch_fused_rows(const Geometry& g, const void* src, void* dst, cons
       case STORAGE_F16DEV: {
         using C = CodecF16Dev;
         using S = C::S;
-        D2Q37_BLOCKS(g, hipLaunchKernelGGL((fused_kernel<C, BS, true>), dim3(ncols * nyb), dim3(BS),
-                                           0, s, static_cast<const S*>(src), static_cast<S*>(dst), g, c, w, cs));
+        if (g.run_off) {
+          D2Q37_BLOCKS(g, hipLaunchKernelGGL((fused_kernel<C, BS, true, false, true>), dim3(ncols * nyb),
+                                             dim3(BS), 0, s, static_cast<const S*>(src), static_cast<S*>(dst), g,
+                                             c, w, cs));
+        } else {
+          D2Q37_BLOCKS(g, hipLaunchKernelGGL((fused_kernel<C, BS, true>), dim3(ncols * nyb), dim3(BS),
+                                             0, s, static_cast<const S*>(src), static_cast<S*>(dst), g, c, w, cs));
+        }
         break;
       }
       default:
         return hipErrorInvalidValue;
     }
+  } else if (g.storage == STORAGE_F16DEV && g.run_off) {
+    using C = CodecF16Dev;
+    using S = C::S;
+    D2Q37_BLOCKS(g, hipLaunchKernelGGL((fused_kernel<C, BS, false, false, true>), dim3(ncols * nyb), dim3(BS),
+                                       0, s, static_cast<const S*>(src), static_cast<S*>(dst), g, c, w, cs));
   } else {
     D2Q37_DISPATCH(g, hipLaunchKernelGGL((fused_kernel<C, BS, false>), dim3(ncols * nyb), dim3(BS),
                                          0, s, static_cast<const S*>(src), static_cast<S*>(dst), g, c, w, cs));

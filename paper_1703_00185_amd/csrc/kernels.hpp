@@ -39,6 +39,10 @@ struct Geometry {
   const double* inv_ref;
   const double* kf;
   int ysplit;
+  // 1 when the 37 runs of a column plus 3 rows on either side span less
+  // than 2^31 bytes, so that one buffer descriptor per column with scalar
+  // run offsets can address them (the binary16 fused kernel uses it)
+  int run_off;
 };
 
 // Shell factors of the deviation-storage reference: K_s(T_lo), K_s(T_hi),

@@ -168,3 +168,32 @@ def test_full_size_planar_equals_column_layout(storage):
     assert np.array_equal(col[0], pla[0])
     assert np.array_equal(col[1], pla[1])
     assert col[1][4] == 0
+
+
+@pytest.mark.timeout(600)
+def test_wide_planar_binary16_equals_column_layout():
+    """Binary16 deviations on 4096 x 8192: in the planar layout the 37
+    population planes of a column span 2.5 GB, past the 2^31-byte range
+    of one buffer descriptor, so the fused kernel addresses each run with
+    its own descriptor; in the column layout one descriptor per column with
+    scalar run offsets covers them.  Both give the same bits after two
+    fused steps, at sampled sites (edge columns, walls, the layer boundary
+    of the reference, random rows) and in the conservation sums."""
+    lx, ly = 4096, LY
+    ns = inputs.rt_config(lx, ly)
+    rt = inputs.rt_perturbation(2, ly)
+    rng = np.random.default_rng(7)
+    cols = [0, 1, 2, 3, lx // 2, lx - 4, lx - 3, lx - 2, lx - 1] + rng.integers(4, lx - 4, 24).tolist()
+    rows = [0, 2, 3, 63, 64, 4093, 4095, 4096, 4098, 4160, ly - 4, ly - 1]
+    xs = np.repeat(np.array(cols, dtype=np.int64), len(rows) + 12)
+    ys = np.concatenate([rows + rng.integers(0, ly, 12).tolist() for _ in cols]).astype(np.int64)
+    out = {}
+    for layout in (lbm.LBM_LAYOUT_COLUMN, lbm.LBM_LAYOUT_PLANAR):
+        with lattice(ns, path=lbm.LBM_PATH_FUSED, layout=layout, storage=lbm.LBM_FP16DEV) as lat:
+            lat.init_rt(rt)
+            lat.step(2)
+            out[layout] = (lat.sites(xs, ys), lat.conservation())
+    col, pla = out[lbm.LBM_LAYOUT_COLUMN], out[lbm.LBM_LAYOUT_PLANAR]
+    assert np.array_equal(col[0], pla[0])
+    assert np.array_equal(col[1], pla[1])
+    assert col[1][4] == 0
