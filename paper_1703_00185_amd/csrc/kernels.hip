@@ -71,10 +71,10 @@ __device__ __forceinline__ int source_column(const Geometry& g, int x, int ex) {
 // in x.  Interior form, for a column x uniform over the work-group: the 37
 // source runs start at uniform (scalar) addresses and all loads share the
 // lane's byte offset.  RUN_OFF: one buffer descriptor per source column
-// (7), based 3 rows before the column's first run, and the run of
-// population l addressed by the scalar offset l * pstride + 3 - e_ly
-// elements (the caller guarantees that a column's runs span less than
-// 2^31 bytes); else one descriptor per population.
+// (7), the lane's offset taken from row y - 3 and the run of population l
+// addressed by the scalar offset l * pstride + 3 - e_ly elements (the
+// caller guarantees that a column's runs span less than 2^31 bytes); else
+// one descriptor per population.
 template <bool WRAP, bool RUN_OFF = false, class C>
 __device__ __forceinline__ void gather_interior(const Geometry& g, const C& cd,
                                                 const typename C::S* __restrict__ src, int x, int y,
@@ -82,18 +82,20 @@ __device__ __forceinline__ void gather_interior(const Geometry& g, const C& cd,
   using S = typename C::S;
   const unsigned off = static_cast<unsigned>(y) * static_cast<unsigned>(sizeof(S));
   if constexpr (RUN_OFF) {
+    // rows are addressed from y - 3 (>= 0 in an interior wavefront), so
+    // that every scalar offset l * pstride + 3 - e_ly is non-negative
     constexpr int kReachY = HALO;              // max |e_y| (the velocity set is symmetric)
+    const unsigned off3 = static_cast<unsigned>(y - kReachY) * static_cast<unsigned>(sizeof(S));
     __amdgpu_buffer_rsrc_t col[2 * HALO + 1];  // source column x - e_x, e_x = -3 .. 3
 #pragma unroll
     for (int e = -HALO; e <= HALO; ++e)
-      col[e + HALO] =
-          buffer_at(src + (static_cast<long long>(source_column<WRAP>(g, x, e)) * g.cstride - kReachY));
+      col[e + HALO] = buffer_at(src + static_cast<long long>(source_column<WRAP>(g, x, e)) * g.cstride);
     const unsigned ps = static_cast<unsigned>(g.pstride) * static_cast<unsigned>(sizeof(S));
 #pragma unroll
     for (int l = 0; l < NPOP; ++l) {
       const unsigned so =
           static_cast<unsigned>(l) * ps + static_cast<unsigned>((kReachY - EY[l]) * static_cast<int>(sizeof(S)));
-      f[l] = cd.dec(ld_at<S>(col[EX[l] + HALO], off, so), l, y - EY[l]);
+      f[l] = cd.dec(ld_at<S>(col[EX[l] + HALO], off3, so), l, y - EY[l]);
     }
   } else {
 #pragma unroll

@@ -94,8 +94,8 @@ int make_layout(const lbm_config* c, Layout* out, std::string* why) {
     g.cstride = NPOP * ny + pad;
     elems = nx * g.cstride;
   }
-  // byte offsets from 3 rows before a column's first run to 3 rows past
-  // its last must fit a buffer descriptor's 31-bit range
+  // byte offsets from a column's start to 3 rows past its last run must
+  // fit a buffer descriptor's 31-bit range
   g.run_off = (NPOP * g.pstride + ny + 2 * HALO) * elem_bytes(g) < (1LL << 31) - 1 ? 1 : 0;
   out->geo = g;
   out->buf_bytes = static_cast<size_t>(round_up(elems * elem_bytes(g), 256));
