@@ -80,7 +80,6 @@ __device__ __forceinline__ void gather_interior(const Geometry& g, const C& cd,
                                                 const typename C::S* __restrict__ src, int x, int y,
                                                 double (&f)[NPOP]) {
   using S = typename C::S;
-  const unsigned off = static_cast<unsigned>(y) * static_cast<unsigned>(sizeof(S));
   if constexpr (RUN_OFF) {
     // rows are addressed from y - 3 (>= 0 in an interior wavefront), so
     // that every scalar offset l * pstride + 3 - e_ly is non-negative
@@ -98,6 +97,7 @@ __device__ __forceinline__ void gather_interior(const Geometry& g, const C& cd,
       f[l] = cd.dec(ld_at<S>(col[EX[l] + HALO], off3, so), l, y - EY[l]);
     }
   } else {
+    const unsigned off = static_cast<unsigned>(y) * static_cast<unsigned>(sizeof(S));
 #pragma unroll
     for (int l = 0; l < NPOP; ++l) {
       const S* base = src + (static_cast<long long>(source_column<WRAP>(g, x, EX[l])) * g.cstride +

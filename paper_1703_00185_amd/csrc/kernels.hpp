@@ -39,8 +39,8 @@ struct Geometry {
   const double* inv_ref;
   const double* kf;
   int ysplit;
-  // 1 when the 37 runs of a column plus 3 rows on either side span less
-  // than 2^31 bytes, so that one buffer descriptor per column with scalar
+  // 1 when the bytes from a column's start to 3 rows past its last run
+  // stay below 2^31, so that one buffer descriptor per column with scalar
   // run offsets can address them (the binary16 fused kernel uses it)
   int run_off;
 };
