@@ -164,7 +164,7 @@ typedef struct {
 int lbm_config_default(lbm_config *cfg, int32_t lx, int32_t ly);
 
 /* Bytes of device memory needed for cfg (two lattice copies with halos,
- * plus the reference of deviation storage: 16 bytes per row and 256); 0
+ * plus the reference of deviation storage: 16 bytes per row and 512); 0
  * if cfg is invalid. */
 size_t lbm_required_bytes(const lbm_config *cfg);
 

@@ -193,6 +193,18 @@ struct CodecF16DevLayer {
   }
 };
 
+// Rows of one temperature layer, for the binary16 interior step: decodes
+// g = rho_ref(y) (1 + d), the population divided by its shell factor
+// (f_l = K_s g_l); only decoding.
+struct CodecF16DevRows {
+  using S = _Float16;
+  const double* ref;
+  __device__ double dec(S v, int, int y) const {
+    const double r = ref[y];
+    return fma(r, static_cast<double>(static_cast<float>(v)), r);
+  }
+};
+
 // acc + k * v for a small integer k known after unrolling.
 __device__ __forceinline__ double add_scaled(double acc, int k, double v) {
   if (k == 0) return acc;
@@ -218,24 +230,49 @@ struct MomentSums {
   double rho, jx, jy, eps;
 };
 
-__device__ __forceinline__ MomentSums moment_sums(const double (&f)[NPOP]) {
+// moment_sums_of takes populations given as f_l = kf(s) g_l: it sums g
+// shell by shell and applies each shell's factor once (UnitFactor: f = g,
+// the same operations as summing f directly).
+struct UnitFactor {
+  static constexpr bool kUnit = true;
+  __device__ double operator()(int) const { return 1.0; }
+};
+struct ShellFactor {
+  static constexpr bool kUnit = false;
+  const __attribute__((address_space(4))) double* k;
+  __device__ double operator()(int s) const { return k[s]; }
+};
+template <class G, class K>
+__device__ __forceinline__ MomentSums moment_sums_of(const G& g, const K& kf) {
   double shell[NSHELL];
   double jx = 0.0, jy = 0.0;
-  shell[0] = f[0];
+  shell[0] = K::kUnit ? g[0] : kf(0) * g[0];
 #pragma unroll
   for (int s = 1; s < NSHELL; ++s) {
     const int lo = SHELL_START[s], hi = SHELL_START[s + 1], mid = (lo + hi) / 2;
-    double acc = 0.0;
+    double acc = 0.0, jxs = 0.0, jys = 0.0;
 #pragma unroll
     for (int l = lo; l < mid; ++l) {
       const int m = lo + hi - 1 - l;  // opposite population: e_m = -e_l
-      const double sum = f[m] + f[l];
-      const double dif = f[m] - f[l];
+      const double sum = g[m] + g[l];
+      const double dif = g[m] - g[l];
       acc = (l == lo) ? sum : acc + sum;
-      jx = add_scaled(jx, EX[m], dif);
-      jy = add_scaled(jy, EY[m], dif);
+      if constexpr (K::kUnit) {
+        jx = add_scaled(jx, EX[m], dif);
+        jy = add_scaled(jy, EY[m], dif);
+      } else {
+        jxs = add_scaled(jxs, EX[m], dif);
+        jys = add_scaled(jys, EY[m], dif);
+      }
     }
-    shell[s] = acc;
+    if constexpr (K::kUnit) {
+      shell[s] = acc;
+    } else {
+      const double k = kf(s);
+      shell[s] = k * acc;
+      jx = fma(k, jxs, jx);
+      jy = fma(k, jys, jy);
+    }
   }
   double rho = shell[0];
   double eps = shell[1];
@@ -244,6 +281,9 @@ __device__ __forceinline__ MomentSums moment_sums(const double (&f)[NPOP]) {
 #pragma unroll
   for (int s = 2; s < NSHELL; ++s) eps = fma(static_cast<double>(SHELL_N2[s]), shell[s], eps);
   return {rho, jx, jy, eps};
+}
+__device__ __forceinline__ MomentSums moment_sums(const double (&f)[NPOP]) {
+  return moment_sums_of(f, UnitFactor{});
 }
 
 // BGK collision of one site (Eqs. 4-6): moments, shifted fields
@@ -255,8 +295,14 @@ __device__ __forceinline__ MomentSums moment_sums(const double (&f)[NPOP]) {
 //   p1 = 1 - U/2 + th (C-4)/2,   p2 = 1/2 - U/4 + th (C-6)/4,
 // U = |u_shift|^2, th = T_shift - 1, C = |c_l|^2.  The even and odd parts
 // of P serve both populations of a pair (s changes sign).
-__device__ __forceinline__ void collide_site(double (&f)[NPOP], const CollideParams& p) {
-  const MomentSums m = moment_sums(f);
+// collide_by hands omega f^eq of each population to the caller: rest(eq)
+// for population 0 and pair(m, eq_m, l, eq_l) for the two populations of
+// a pair.  With SHIFT, c(s) is subtracted from each shell's constant term
+// e0, so the caller receives omega f^eq_l - c(s) without a subtraction per
+// population.
+template <bool SHIFT, class Rest, class Pair, class Shift>
+__device__ __forceinline__ void collide_by(const MomentSums& m, const CollideParams& p, Rest&& rest, Pair&& pair,
+                                           const Shift& c) {
   const double inv_rho = 1.0 / m.rho;
   const double ux = R * m.jx * inv_rho;
   const double uy = R * m.jy * inv_rho;
@@ -277,14 +323,15 @@ __device__ __forceinline__ void collide_site(double (&f)[NPOP], const CollidePar
   const double a2 = (0.5 - 0.25 * U) - 1.5 * th;
   const double b2 = 0.25 * th;
   const double rw = m.rho * p.omega;
-  const double om1 = p.one_minus_omega;
 
-  f[0] = fma(om1, f[0], (rw * W_SHELL[0]) * a0);
+  if constexpr (SHIFT) rest((rw * W_SHELL[0]) * a0 - c(0));
+  else rest((rw * W_SHELL[0]) * a0);
 #pragma unroll
   for (int s = 1; s < NSHELL; ++s) {
     const double C = R2 * static_cast<double>(SHELL_N2[s]);
     const double cs = rw * W_SHELL[s];
-    const double e0 = cs * fma(C, fma(C, d0, b0), a0);
+    double e0 = cs * fma(C, fma(C, d0, b0), a0);
+    if constexpr (SHIFT) e0 = e0 - c(s);
     const double e2 = cs * fma(C, b2, a2);
     const double e4 = cs * (1.0 / 24.0);
     const double o1 = cs * fma(C, b1, a1);
@@ -303,10 +350,21 @@ __device__ __forceinline__ void collide_site(double (&f)[NPOP], const CollidePar
       const double ss = sv * sv;
       const double even = fma(ss, fma(ss, e4, e2), e0);
       const double odd = sv * fma(ss, o3, o1);
-      f[mm] = fma(om1, f[mm], even + odd);
-      f[l] = fma(om1, f[l], even - odd);
+      pair(mm, even + odd, l, even - odd);
     }
   }
+}
+
+__device__ __forceinline__ void collide_site(double (&f)[NPOP], const CollideParams& p) {
+  const MomentSums m = moment_sums(f);
+  const double om1 = p.one_minus_omega;
+  collide_by<false>(
+      m, p, [&](double eq) { f[0] = fma(om1, f[0], eq); },
+      [&](int a, double ea, int b, double eb) {
+        f[a] = fma(om1, f[a], ea);
+        f[b] = fma(om1, f[b], eb);
+      },
+      UnitFactor{});
 }
 
 // bc of one wall-row site: rho = f_0 + ... + f_36 (left fold), f_l = rho K_l.
