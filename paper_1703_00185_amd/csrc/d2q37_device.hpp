@@ -193,14 +193,17 @@ struct CodecF16DevLayer {
   }
 };
 
-// Rows of one temperature layer, for the binary16 interior step: decodes
-// g = rho_ref(y) (1 + d), the population divided by its shell factor
-// (f_l = K_s g_l); only decoding.
-struct CodecF16DevRows {
+// Rows of one temperature layer, for the binary16 interior step at row y:
+// decodes a population pulled from row y' of the same layer in units of
+// the destination's reference, g = f_l / (K_s rho_ref(y)) =
+// (rho_ref(y') / rho_ref(y)) (1 + d) (both rows have the layer's K_s, which
+// cancels).  iy = 1 / rho_ref(y).
+struct CodecF16DevRatio {
   using S = _Float16;
   const double* ref;
-  __device__ double dec(S v, int, int y) const {
-    const double r = ref[y];
+  double iy;
+  __device__ double dec(S v, int, int ys) const {
+    const double r = ref[ys] * iy;
     return fma(r, static_cast<double>(static_cast<float>(v)), r);
   }
 };
@@ -300,9 +303,14 @@ __device__ __forceinline__ MomentSums moment_sums(const double (&f)[NPOP]) {
 // a pair.  With SHIFT, c(s) is subtracted from each shell's constant term
 // e0, so the caller receives omega f^eq_l - c(s) without a subtraction per
 // population.
-template <bool SHIFT, class Rest, class Pair, class Shift>
+// w(s): the weight of shell s (StdWeight: W_s); the binary16 interior step
+// passes W_s / K_s, which puts f^eq in units of the reference.
+struct StdWeight {
+  __device__ double operator()(int s) const { return W_SHELL[s]; }
+};
+template <bool SHIFT, class Rest, class Pair, class Shift, class Weight = StdWeight>
 __device__ __forceinline__ void collide_by(const MomentSums& m, const CollideParams& p, Rest&& rest, Pair&& pair,
-                                           const Shift& c) {
+                                           const Shift& c, const Weight& w = StdWeight{}) {
   const double inv_rho = 1.0 / m.rho;
   const double ux = R * m.jx * inv_rho;
   const double uy = R * m.jy * inv_rho;
@@ -324,12 +332,12 @@ __device__ __forceinline__ void collide_by(const MomentSums& m, const CollidePar
   const double b2 = 0.25 * th;
   const double rw = m.rho * p.omega;
 
-  if constexpr (SHIFT) rest((rw * W_SHELL[0]) * a0 - c(0));
-  else rest((rw * W_SHELL[0]) * a0);
+  if constexpr (SHIFT) rest((rw * w(0)) * a0 - c(0));
+  else rest((rw * w(0)) * a0);
 #pragma unroll
   for (int s = 1; s < NSHELL; ++s) {
     const double C = R2 * static_cast<double>(SHELL_N2[s]);
-    const double cs = rw * W_SHELL[s];
+    const double cs = rw * w(s);
     double e0 = cs * fma(C, fma(C, d0, b0), a0);
     if constexpr (SHIFT) e0 = e0 - c(s);
     const double e2 = cs * fma(C, b2, a2);

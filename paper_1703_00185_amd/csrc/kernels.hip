@@ -271,28 +271,23 @@ __global__ void __launch_bounds__(BLOCK) collide_kernel(const typename C::S* __r
   store_column_site(g, cd, dst, x, y, f);
 }
 
-// Interior wavefront of one temperature layer, binary16 deviations.  The
-// stored d_l are widened to g_l = rho_ref(y - e_ly) (1 + d_l), so that
-// f_l = K_s g_l with the layer's wavefront-uniform K_s: the moment sums
-// take K_s once per shell, the relaxation (1 - omega) f_l + omega f^eq_l
-// takes (1 - omega) K_s from the reference table (omk), and the reference
-// of the destination row, c_l = K_s rho_ref(y), comes off each shell's
-// constant equilibrium term, so that the stored
-// q_l = ((1 - omega) K_s g_l + omega f^eq_l - c_l) (K_s rho_ref(y))^-1
-// costs one multiply-add and one multiply.  Same binary64 result as
-// decoding, colliding and encoding f to within a few roundings (about
-// 30 VALU instructions per site fewer); each q_l is stored as soon as it
-// is computed.
+// Interior wavefront of one temperature layer, binary16 deviations, in
+// units of the destination's reference c_l = K_s rho_ref(y): the stored
+// d_l widen to g_l = (rho_ref(y - e_ly) / rho_ref(y)) (1 + d_l), so that
+// f_l / c_l = g_l and f_l = K_s rho_ref(y) g_l.  The moment sums apply K_s
+// once per shell (density in units of rho_ref(y); velocity and
+// temperature are ratios and come out unscaled), the equilibrium takes the
+// weights W_s / K_s from the reference table (wk), and the stored
+// q_l = f_new,l / c_l - 1 = (1 - omega) g_l + (omega f^eq_l / c_l - 1) is
+// one multiply-add, the -1 folded into each shell's constant term.
 template <bool WRAP, bool RUN_OFF>
-__device__ __forceinline__ void fused_layer_interior(const Geometry& g, const CodecF16DevLayer& lc, ConstD* omk,
+__device__ __forceinline__ void fused_layer_interior(const Geometry& g, const CodecF16DevLayer& lc, ConstD* wk,
                                                      const _Float16* __restrict__ src, _Float16* __restrict__ dst,
                                                      const CollideParams& p, int x, int y) {
   using S = _Float16;
   double gv[NPOP];
-  gather_interior<WRAP, RUN_OFF>(g, CodecF16DevRows{lc.ref}, src, x, y, gv);
+  gather_interior<WRAP, RUN_OFF>(g, CodecF16DevRatio{lc.ref, lc.inv_ref[y]}, src, x, y, gv);
   const MomentSums m = moment_sums_of(gv, ShellFactor{lc.k});
-  const double ry = lc.ref[y];
-  const double iy = lc.inv_ref[y];
   const unsigned off = static_cast<unsigned>(y) * static_cast<unsigned>(sizeof(S));
   const unsigned ps = static_cast<unsigned>(g.pstride) * static_cast<unsigned>(sizeof(S));
   S* col = dst + static_cast<long long>(x + HALO) * g.cstride;
@@ -302,15 +297,14 @@ __device__ __forceinline__ void fused_layer_interior(const Geometry& g, const Co
     if constexpr (RUN_OFF) st_nt_at<S>(r, off, static_cast<unsigned>(l) * ps, v);
     else st_nt(col + static_cast<long long>(l) * g.pstride, off, v);
   };
+  const double om1 = p.one_minus_omega;
   collide_by<true>(
-      m, p, [&](double eq) { put(0, fma(omk[0], gv[0], eq) * (lc.kinv[0] * iy)); },
+      m, p, [&](double eq) { put(0, fma(om1, gv[0], eq)); },
       [&](int a, double ea, int b, double eb) {
-        const int s = shell_of(a);
-        const double inv = lc.kinv[s] * iy;
-        put(a, fma(omk[s], gv[a], ea) * inv);
-        put(b, fma(omk[s], gv[b], eb) * inv);
+        put(a, fma(om1, gv[a], ea));
+        put(b, fma(om1, gv[b], eb));
       },
-      [&](int s) { return lc.k[s] * ry; });
+      [](int) { return 1.0; }, ShellFactor{wk});
 }
 
 // One site of the fused step (below), with the codec cd.
@@ -345,7 +339,7 @@ __device__ __forceinline__ void fused_site(const Geometry& g, const C& cd, const
     const ConstD* kf = (ConstD*)(g.kf);
     const CodecF16DevLayer lc{g.ref, g.inv_ref, kf + (hi ? KF_HI : KF_LO), kf + (hi ? KF_INV_HI : KF_INV_LO)};
     if (interior_wave(g, ywave)) {
-      fused_layer_interior<WRAP, RUN_OFF>(g, lc, kf + (hi ? KF_OMK_HI : KF_OMK_LO), src, dst, c, x, y);
+      fused_layer_interior<WRAP, RUN_OFF>(g, lc, kf + (hi ? KF_WK_HI : KF_WK_LO), src, dst, c, x, y);
       return;
     } else {
       const int yc = y < g.ly ? y : g.ly - 1;

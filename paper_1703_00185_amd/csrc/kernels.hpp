@@ -46,10 +46,10 @@ struct Geometry {
 };
 
 // Shell factors of the deviation-storage reference: K_s(T_lo), K_s(T_hi),
-// 1 / K_s(T_lo), 1 / K_s(T_hi), (1 - omega) K_s(T_lo), (1 - omega)
-// K_s(T_hi), NSHELL doubles each.
+// 1 / K_s(T_lo), 1 / K_s(T_hi), W_s / K_s(T_lo), W_s / K_s(T_hi), NSHELL
+// doubles each.
 constexpr int KF_LO = 0, KF_HI = NSHELL, KF_INV_LO = 2 * NSHELL, KF_INV_HI = 3 * NSHELL;
-constexpr int KF_OMK_LO = 4 * NSHELL, KF_OMK_HI = 5 * NSHELL;
+constexpr int KF_WK_LO = 4 * NSHELL, KF_WK_HI = 5 * NSHELL;
 constexpr int KF_LEN = 6 * NSHELL;
 
 // Scalars of the collision (Eqs. 4-6): omega = 1/tau, the shift tau*g of

@@ -243,7 +243,7 @@ int run_phase(lbm_handle* h, int phase) {
 // t_hi on rows y >= ysplit.  Uploads rho, 1 / rho and the shell factors
 // K_s(t_lo), K_s(t_hi) (the wall factor of the first population of shell
 // s: the zero-velocity equilibrium per unit density), their reciprocals
-// and their products with 1 - omega, each rounded once.  Keeps host copies for
+// and the shell weights divided by them, each rounded once.  Keeps host copies for
 // lbm_get_reference.  Synchronises the handle's stream.
 int set_reference_table(lbm_handle* h, const double* rho, double t_lo, double t_hi, int ysplit) {
   const int ly = h->geo.ly;
@@ -265,8 +265,8 @@ int set_reference_table(lbm_handle* h, const double* rho, double t_lo, double t_
       return fail(h, LBM_EINVAL, "the zero-velocity equilibrium is not positive at the layer temperatures");
     kf[KF_INV_LO + sh] = 1.0 / kf[KF_LO + sh];
     kf[KF_INV_HI + sh] = 1.0 / kf[KF_HI + sh];
-    kf[KF_OMK_LO + sh] = h->cp.one_minus_omega * kf[KF_LO + sh];
-    kf[KF_OMK_HI + sh] = h->cp.one_minus_omega * kf[KF_HI + sh];
+    kf[KF_WK_LO + sh] = W_SHELL[sh] / kf[KF_LO + sh];
+    kf[KF_WK_HI + sh] = W_SHELL[sh] / kf[KF_HI + sh];
   }
   LBM_HIP(h, hipMemcpyAsync(const_cast<double*>(h->geo.ref), rows.data(), ly * sizeof(double),
                             hipMemcpyHostToDevice, h->stream));
