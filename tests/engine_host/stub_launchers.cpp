@@ -3,10 +3,14 @@
 // the stream runs it, touches the memory the real kernel would read and
 // write (first and last element of each lattice copy it uses, every element
 // of staging buffers), so that a launch that runs after its memory was freed
-// is reported by the sanitizer.  The engine's advance kernel is simulated
-// exactly (it is the state the host reads back).
+// is reported by the sanitizer.  The engine's step kernel walks its tile
+// table as on the GPU and aborts if a tile would fall outside its slot's
+// lattice; the advance kernel is simulated exactly (it is the state the
+// host reads back).
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "engine.hpp"
@@ -40,8 +44,19 @@ void enqueue(hipStream_t s, std::function<void()> op) { hipstub::of(s).ops.push_
 
 size_t last_of(const Geometry& g) { return last_byte(g.pstride, g.cstride, g.lx, g.ly, g.storage); }
 
-// Engine kernels.  The step kernel touches both copies of every active
-// slot with steps left; the advance kernel flips and counts as on the GPU.
+// Engine kernels.  The step kernel walks the tile table as the GPU kernel
+// does and checks what its indexing relies on: the active slots of its
+// storage type in table order, prefix sums from 0 to the total, and for
+// every slot with steps left a tile count of lx * ceil(ly / 64), so that
+// every tile's column and row block lie inside that slot's lattice; it
+// touches each column's first and last element in both copies of every
+// slot it steps.  The advance kernel flips and counts as on the GPU.
+void sim_check(bool ok, const char* what) {
+  if (ok) return;
+  std::fprintf(stderr, "engine step kernel stand-in: %s\n", what);
+  std::abort();
+}
+template <int STORAGE>
 void engine_step_sim(const std::vector<std::vector<unsigned char>>& a) {
   const SlotDesc* slots;
   const int* table;
@@ -50,12 +65,33 @@ void engine_step_sim(const std::vector<std::vector<unsigned char>>& a) {
   std::memcpy(&table, a[1].data(), sizeof table);
   std::memcpy(&m, a[2].data(), sizeof m);
   const int n = table[0];
+  const int total = table[1];
+  if (n <= 0 || total <= 0) return;
+  const int* order = table + 2;
+  const int* start = table + 2 + m;
+  sim_check(n <= m, "more active slots than slots");
+  sim_check(start[0] == 0 && start[n] == total, "prefix sums do not run from 0 to the tile total");
   for (int k = 0; k < n; ++k) {
-    const SlotDesc& d = slots[table[2 + k]];
-    if (d.steps_left <= 0) continue;
-    const size_t last = last_byte(d.pstride, d.cstride, d.lx, d.ly, d.storage);
-    touch_read(d.buf[d.cur], last);
-    touch_write(d.buf[d.cur ^ 1], last);
+    sim_check(start[k] <= start[k + 1], "prefix sums decrease");
+    sim_check(order[k] >= 0 && order[k] < m, "slot id out of range");
+    const SlotDesc& d = slots[order[k]];
+    sim_check(d.storage == STORAGE, "slot of another storage type in this kernel's table");
+    if (d.steps_left <= 0) continue;  // the kernel skips it
+    sim_check(d.ny_waves == (d.ly + 63) / 64, "row blocks per column do not match ly");
+    sim_check(static_cast<long long>(start[k + 1]) - start[k] == static_cast<long long>(d.lx) * d.ny_waves,
+              "tile count of a stepped slot does not match its lattice");
+    const size_t e = elem(d.storage);
+    for (int x = 0; x < d.lx; ++x) {
+      const long long col = static_cast<long long>(x + 3) * d.cstride;
+      const size_t first = static_cast<size_t>(col) * e;
+      const size_t last = static_cast<size_t>(col + 36 * d.pstride + (d.ly - 1)) * e;
+      const unsigned char* src = reinterpret_cast<const unsigned char*>(d.buf[d.cur]);
+      unsigned char* dst = reinterpret_cast<unsigned char*>(d.buf[d.cur ^ 1]);
+      g_sink = src[first];
+      g_sink = src[last];
+      dst[first] = 0;
+      dst[last] = 0;
+    }
   }
 }
 void engine_advance_sim(const std::vector<std::vector<unsigned char>>& a) {
@@ -79,10 +115,10 @@ char g_step_f64, g_step_f32, g_advance;  // stand-in kernel "functions"
 
 struct Register {
   Register() {
-    for (const void* f : {static_cast<const void*>(&g_step_f64), static_cast<const void*>(&g_step_f32)}) {
-      hipstub::sims().push_back({f, engine_step_sim});
+    hipstub::sims().push_back({&g_step_f64, engine_step_sim<STORAGE_F64>});
+    hipstub::sims().push_back({&g_step_f32, engine_step_sim<STORAGE_F32>});
+    for (const void* f : {static_cast<const void*>(&g_step_f64), static_cast<const void*>(&g_step_f32)})
       hipstub::arg_sizes().push_back({f, {sizeof(void*), sizeof(void*), sizeof(int)}});
-    }
     hipstub::sims().push_back({&g_advance, engine_advance_sim});
     hipstub::arg_sizes().push_back({&g_advance, {sizeof(void*), sizeof(int), sizeof(void*)}});
   }

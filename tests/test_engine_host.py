@@ -5,7 +5,9 @@ UndefinedBehaviorSanitizer, on a CPU stand-in of the HIP runtime (no GPU).
 code in which every asynchronous copy, kernel launch and graph launch is
 queued on its stream and runs only at the synchronisation that covers it;
 `stub_launchers.cpp` stands in for the kernels (touching the memory each
-would read and write, and simulating the engine's advance kernel exactly).
+would read and write, walking the engine step kernel's tile table with
+checks that every tile of a stepped lattice lies inside it, and simulating
+the engine's advance kernel exactly).
 `join_leave.cpp` drives lbm_api.cpp and engine_api.cpp, unchanged, through
 the C ABI with the call sequences of the GPU engine tests: mixes under
 several tilings, lattices joining and leaving mid-run with slot reuse, read
