@@ -18,8 +18,9 @@ busy, p50/p99 completion latency (completion minus arrival), and the same
 latencies for a one-request-at-a-time plain FP64 server under the same
 arrivals: run on the GPU (FIFO, each request a plain FP64 lattice stepped
 alone) and, beside it, simulated from FP64 throughput measured per lattice
-size.  A sample of served results is recomputed alone and compared bit for
-bit.  Prints one JSON line.
+size.  A sample of served results (half of them small lattices, half of a
+million sites or more, kept on the GPU until the run ends) is recomputed
+alone and compared bit for bit.  Prints one JSON line.
 
 Usage: python -m paper_1703_00185_amd.serve [--requests 5000] [--load 0.8]
 """
@@ -75,10 +76,14 @@ class Server:
         of "ps").
       * "ps": every resident lattice is stepped (processor sharing).
     Events (time, kind, request id, slot): "admit" (resident), "join" and
-    "leave" (on and off the engine), "retire" (finished, memory freed)."""
+    "leave" (on and off the engine), "retire" (finished, memory freed).
+    Requests in `keep` have their final populations kept: read back to the
+    host at retirement, or with keep_lattices the finished lattices
+    themselves, which then stay in device memory outside the budget until
+    the caller closes them."""
 
     def __init__(self, lbm, inputs, budget_bytes: int, max_slots: int, chunk: int, keep=(),
-                 policy: str = "srpt", fill_sites: int = 8_000_000):
+                 policy: str = "srpt", fill_sites: int = 8_000_000, keep_lattices: bool = False):
         if policy not in ("srpt", "ps"):
             raise ValueError("policy must be 'srpt' or 'ps'")
         self.lbm, self.inputs = lbm, inputs
@@ -89,6 +94,10 @@ class Server:
         self.engine = lbm.Engine(max_slots=max_slots)
         self.max_slots = max_slots
         self.keep = set(keep)       # request ids whose final populations are kept
+        # keep_lattices: keep those lattices themselves (off the engine, not
+        # closed; the caller reads and closes them), so that keeping a large
+        # result costs the loop no copy to the host
+        self.keep_lattices = keep_lattices
         self.kept = {}
         self.used = 0
         self.events = []
@@ -173,11 +182,14 @@ class Server:
                 r = e["r"]
                 done[rid] = now
                 site_steps += r.lx * r.ly * r.steps
-                if rid in self.keep:
+                if rid in self.keep and not self.keep_lattices:
                     self.kept[rid] = e["lat"].get()
                 self.engine.remove(e["slot"])
                 self.events.append((now, "retire", rid, e["slot"]))
-                e["lat"].close()
+                if rid in self.keep and self.keep_lattices:
+                    self.kept[rid] = e["lat"]
+                else:
+                    e["lat"].close()
                 self.used -= e["bytes"]
         makespan = time.perf_counter() - t0
         self.engine.close()
@@ -289,10 +301,17 @@ def serve_workload(lbm, inputs, requests: int = 5000, seed: int = 0, load: float
 
     served, identical, fill = None, None, None
     if serve:
+        # half of the checked requests from the small lattices, half from
+        # those of a million sites or more (the largest the workload draws)
         rng = np.random.default_rng(seed + 7)
         small = [r.rid for r in reqs if r.lx * r.ly <= 65536]
-        keep = set(rng.choice(small, size=min(check, len(small)), replace=False).tolist()) if small else set()
-        srv = Server(lbm, inputs, int(budget_gb * 2**30), max_slots, chunk, keep, policy=policy)
+        large = [r.rid for r in reqs if r.lx * r.ly >= 1 << 20]
+        n_large = min(check // 2, len(large))
+        keep = set(rng.choice(large, size=n_large, replace=False).tolist()) if n_large else set()
+        if small:
+            keep |= set(rng.choice(small, size=min(check - n_large, len(small)), replace=False).tolist())
+        srv = Server(lbm, inputs, int(budget_gb * 2**30), max_slots, chunk, keep, policy=policy,
+                     keep_lattices=True)
         srv.engine.set_tiling(block, groups, sched)
         fill = srv.fill_sites
         done, makespan, site_steps = srv.run(reqs)
@@ -308,16 +327,21 @@ def serve_workload(lbm, inputs, requests: int = 5000, seed: int = 0, load: float
                   "latency_p99_s": percentile(lat_served, 99),
                   "latency_mean_s": float(np.mean(lat_served))}
 
-        # identical alone and in the mix
+        # identical alone and in the mix (every population, bit for bit)
         mismatches = 0
         for rid in sorted(srv.kept):
             r = reqs[rid]
+            mixed = srv.kept[rid]
+            got = mixed.get()
+            mixed.close()
             lat = lbm.Lattice(srv.config(r))
             lat.init_rt(inputs.rt_perturbation(r.seed, r.ly))
             lat.step(r.steps)
-            mismatches += int(not np.array_equal(lat.get(), srv.kept[rid]))
+            mismatches += int(not np.array_equal(lat.get(), got))
             lat.close()
-        identical = {"checked": len(srv.kept), "mismatches": mismatches}
+            del got
+        identical = {"checked": len(srv.kept), "mismatches": mismatches,
+                     "largest_sites": max((reqs[rid].lx * reqs[rid].ly for rid in srv.kept), default=0)}
 
     # one request at a time, plain FP64, same arrivals
     grid = sorted({(64 * 2 ** k, 128 * 2 ** k) for k in range(5)} |
