@@ -108,19 +108,45 @@ __device__ __forceinline__ void gather_interior(const Geometry& g, const C& cd,
 }
 
 // General form, for wavefronts touching the walls: a source row beyond a
-// wall is replaced by the opposite population of the same site.
-template <bool WRAP, class C>
+// wall is replaced by the opposite population of the same site.  Each
+// population is read through its wavefront-uniform run base at the lane's
+// row, clamped into the lattice, and the lanes whose source lies beyond a
+// wall (at most three rows) read the opposite population of their own site
+// in a second, masked load.  LANE_ADDR: one load per population from a
+// per-lane 64-bit index instead (the propagate kernel, whose interior
+// wavefronts are so short that the scalar address set-up the uniform form
+// shares with them would slow the whole kernel).
+template <bool WRAP, bool LANE_ADDR = false, class C>
 __device__ __forceinline__ void gather_wall(const Geometry& g, const C& cd,
                                             const typename C::S* __restrict__ src, int x, int y,
                                             double (&f)[NPOP]) {
+  using S = typename C::S;
   const int X = x + HALO;
+  if constexpr (LANE_ADDR) {
 #pragma unroll
-  for (int l = 0; l < NPOP; ++l) {
-    const int ys = y - EY[l];
-    const bool inside = (ys >= 0) && (ys < g.ly);
-    const long long idx =
-        inside ? run_of(g, l, source_column<WRAP>(g, x, EX[l])) + ys : run_of(g, opp_of(l), X) + y;
-    f[l] = cd.dec(src[idx], l, inside ? ys : y);  // opp(l) shares w_l
+    for (int l = 0; l < NPOP; ++l) {
+      const int ys = y - EY[l];
+      const bool inside = (ys >= 0) && (ys < g.ly);
+      const long long idx =
+          inside ? run_of(g, l, source_column<WRAP>(g, x, EX[l])) + ys : run_of(g, opp_of(l), X) + y;
+      f[l] = cd.dec(src[idx], l, inside ? ys : y);  // opp(l) shares w_l
+    }
+  } else {
+    const unsigned off = static_cast<unsigned>(y) * static_cast<unsigned>(sizeof(S));
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) {
+      const S* run = src + run_of(g, l, source_column<WRAP>(g, x, EX[l]));
+      if (EY[l] == 0) {
+        f[l] = cd.dec(ld(run, off), l, y);
+        continue;
+      }
+      const int ys = y - EY[l];
+      const bool inside = (ys >= 0) && (ys < g.ly);
+      const int yc = min(max(ys, 0), g.ly - 1);
+      S v = ld(run, static_cast<unsigned>(yc) * static_cast<unsigned>(sizeof(S)));
+      if (!inside) v = ld(src + run_of(g, opp_of(l), X), off);
+      f[l] = cd.dec(v, l, inside ? ys : y);  // opp(l) shares w_l
+    }
   }
 }
 
@@ -235,7 +261,7 @@ __global__ void __launch_bounds__(BLOCK) propagate_kernel(const typename C::S* _
   if (interior_wave(g, ywave)) {
     gather_interior<false>(g, cd, src, x, y, f);
   } else {
-    gather_wall<false>(g, cd, src, x, y < g.ly ? y : g.ly - 1, f);
+    gather_wall<false, true>(g, cd, src, x, y < g.ly ? y : g.ly - 1, f);
   }
   if (y < g.ly) store_column_site(g, cd, dst, x, y, f);
 }
