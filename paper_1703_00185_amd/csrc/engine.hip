@@ -60,19 +60,32 @@ __device__ __forceinline__ void gather_wrap_interior(SlotView& d, const C& cd,
   }
 }
 
+// Wall wavefronts: each population through its uniform run base at the
+// lane's row clamped into the lattice; the lanes whose source lies beyond a
+// wall (at most three rows) read the opposite population of their own site
+// in a second, masked load.
 template <class C>
 __device__ __forceinline__ void gather_wrap_wall(SlotView& d, const C& cd,
                                                  const GLOBAL_AS typename C::S* src, int x, int y,
                                                  double (&f)[NPOP]) {
+  using S = typename C::S;
+  const unsigned uy = static_cast<unsigned>(y);
 #pragma unroll
   for (int l = 0; l < NPOP; ++l) {
+    const int col = wrap_col(x, EX[l], d.lx) + HALO;
+    const GLOBAL_AS S* run =
+        src + (static_cast<long long>(l) * d.pstride + static_cast<long long>(col) * d.cstride);
+    if (EY[l] == 0) {
+      f[l] = cd.dec(run[uy], l, y);
+      continue;
+    }
     const int ys = y - EY[l];
     const bool inside = (ys >= 0) && (ys < d.ly);
-    const long long col = wrap_col(x, EX[l], d.lx) + HALO;
-    const long long idx = inside
-        ? static_cast<long long>(l) * d.pstride + col * d.cstride + ys
-        : static_cast<long long>(opp_of(l)) * d.pstride + static_cast<long long>(x + HALO) * d.cstride + y;
-    f[l] = cd.dec(src[idx], l, inside ? ys : y);
+    const unsigned yc = static_cast<unsigned>(min(max(ys, 0), d.ly - 1));
+    S v = run[yc];
+    if (!inside)
+      v = src[static_cast<long long>(opp_of(l)) * d.pstride + static_cast<long long>(x + HALO) * d.cstride + uy];
+    f[l] = cd.dec(v, l, inside ? ys : y);
   }
 }
 
@@ -135,8 +148,10 @@ __device__ __forceinline__ int find_slot(const int* start, int n, int t) {
 
 // One kernel per storage type (C): each walks the tile table of the
 // lattices of its type.  Wavefronts never synchronise with each other.
+// Bounded to 128 VGPRs (4 wavefronts per SIMD), which it fits without
+// spilling.
 template <class C, int BLOCK, int SCHED>
-__global__ void __launch_bounds__(BLOCK) engine_step_kernel(const SlotDesc* __restrict__ slots,
+__global__ void __launch_bounds__(BLOCK, 4) engine_step_kernel(const SlotDesc* __restrict__ slots,
                                                             const int* __restrict__ table,
                                                             int max_slots) {
   constexpr int W = BLOCK / WAVE;  // wavefronts per work-group
