@@ -197,3 +197,57 @@ def test_wide_planar_binary16_equals_column_layout():
     assert np.array_equal(col[0], pla[0])
     assert np.array_equal(col[1], pla[1])
     assert col[1][4] == 0
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("storage", [lbm.LBM_FP64, lbm.LBM_FP16DEV])
+def test_tall_narrow_lattice_step_at_sampled_sites(storage):
+    """The narrowest lattice (Lx = 3: every column pulls across the periodic
+    boundary on both sides) at 2^17 rows (2048 wavefronts per column, row
+    offsets far past one work-group tile), weak gravity so the hydrostatic
+    density stays within a factor of 1.2: one fused step at sampled rows of
+    all three columns against the oracle (FP64 to the tolerance; binary16
+    deviations to 2 units in the last place of the oracle's stored step),
+    and two fused steps equal to two separate steps."""
+    lx, ly = 3, 1 << 17
+    ns = inputs.rt_config(lx, ly, gravity=1e-6)
+    rt = inputs.rt_perturbation(3, ly)
+    rng = np.random.default_rng(11)
+    rows = np.concatenate([[0, 1, 2, 3, 63, 64, ly // 2 - 1, ly // 2, ly // 2 + 1, ly - 4, ly - 3, ly - 1],
+                           rng.integers(0, ly, 40)])
+    xs = np.repeat(np.arange(lx, dtype=np.int64), rows.size)
+    ys = np.tile(rows.astype(np.int64), lx)
+    f0 = oracle.init_rt(lx, ly, ns, rt)
+    ref_rows = state = None
+    if storage == lbm.LBM_FP16DEV:
+        flat = inputs.flat_interface(ly)
+        _, rho = oracle.rt_fields(1, ly, ns, flat)
+        state = (rho[0].copy(), ns.t_bottom, ns.t_top, int(np.ceil(flat.y_center)))
+        ref_rows = oracle.fp16dev_reference(*state)
+        f0 = oracle.stored(f0, "fp16dev", ref_rows)
+    want = oracle.step_sites(f0, ns, xs, ys)
+    out = {}
+    for path in (lbm.LBM_PATH_FUSED, lbm.LBM_PATH_SEPARATE):
+        with lattice(ns, path=path, storage=storage) as lat:
+            lat.init_rt(rt)
+            if storage == lbm.LBM_FP16DEV:
+                # the oracle's reference and stored initial state, so that
+                # the step alone is compared
+                lbm.lbm_set_reference(lat.h, *state)
+                lat.set(f0)
+            lat.step(1)
+            out[path, 1] = lat.sites(xs, ys)
+            lat.step(1)
+            out[path, 2] = lat.sites(xs, ys)
+            cons = lat.conservation()
+        assert cons[4] == 0
+    got = out[lbm.LBM_PATH_FUSED, 1]
+    if storage == lbm.LBM_FP64:
+        e = err_metric(got, want)
+        note(f"{lx}x{ly} fp64: one fused step, err {e:.2e}")
+        assert e < FP64_TOL
+        assert np.array_equal(out[lbm.LBM_PATH_FUSED, 2], out[lbm.LBM_PATH_SEPARATE, 2])
+    else:
+        u = _ulps_apart(got, _stored_at_sites(want, "fp16dev", ref_rows, ys), "fp16dev", ref_rows, ys)
+        note(f"{lx}x{ly} fp16dev: one fused step within {u:.0f} ulp of the oracle's stored step")
+        assert u <= 2
