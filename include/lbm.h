@@ -132,7 +132,7 @@ typedef struct {
   int32_t block;     /* work-group size of the lattice kernels: 64, 128,
                         256, 512 or 1024; 0 selects the default: 64 when
                         Lx * ceil(Ly / 64) < 1024 (fewer wavefronts than
-                        SIMDs), else 512 (FP64), 256 (FP32), 128 (FP16DEV),
+                        SIMDs), else 512 (FP64), 256 (FP32), 64 (FP16DEV),
                         lowered to the smallest power of two >= Ly when
                         that is less */
   int32_t ny_pad;    /* extra elements in the row pitch NY; < 0 default */

@@ -32,7 +32,7 @@ struct Layout {
 };
 
 // Default work-group size: the fastest measured on the 2048 x 8192 fused
-// step per storage type (512 for binary64, 256 for binary32, 128 for
+// step per storage type (512 for binary64, 256 for binary32, 64 for
 // binary16 deviations), but no more rows than the smallest power of two
 // covering ly, so that short columns do not idle most of the lanes.  A
 // lattice with fewer wavefronts than an MI355X has SIMDs (256 CUs x 4)
@@ -40,7 +40,7 @@ struct Layout {
 int default_block(int storage, int lx, int ly) {
   const long long waves = static_cast<long long>(lx) * ((ly + 63) / 64);
   if (waves < 1024) return 64;
-  const int pref = storage == LBM_FP64 ? 512 : storage == LBM_FP32 ? 256 : 128;
+  const int pref = storage == LBM_FP64 ? 512 : storage == LBM_FP32 ? 256 : 64;
   int b = 64;
   while (b < pref && b < ly) b *= 2;
   return b;

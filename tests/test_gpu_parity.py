@@ -411,7 +411,7 @@ def test_bandwidth_probe_rejects_bad_arguments():
 
 
 @pytest.mark.parametrize("storage,lx,ly,want", [
-    (lbm.LBM_FP64, 8, 8192, 512), (lbm.LBM_FP32, 8, 8192, 256), (lbm.LBM_FP16DEV, 8, 8192, 128),
+    (lbm.LBM_FP64, 8, 8192, 512), (lbm.LBM_FP32, 8, 8192, 256), (lbm.LBM_FP16DEV, 8, 8192, 64),
     (lbm.LBM_FP64, 256, 300, 512), (lbm.LBM_FP64, 256, 200, 256), (lbm.LBM_FP64, 512, 128, 128),
     (lbm.LBM_FP32, 1024, 100, 128), (lbm.LBM_FP64, 1024, 6, 64),
     # fewer wavefronts (lx * ceil(ly / 64)) than the 1024 SIMDs: one-wavefront groups
