@@ -8,8 +8,9 @@ the whole lattice.  Inputs are resident in HBM before the timed region.
 Beside it, for comparison: the same step in the planar layout, the
 separate path (pbc, propagate, bc, collide), FP32 and FP16-deviation
 storage with their field errors against the FP64 path after the same
-steps, the region split, the 64 x 128 workload (plain and graph-replayed
-launches), copy probes of the attainable bandwidth, the batched ensemble
+steps, the region split, the two-step path (two steps per launch pair,
+each site read and written once per two steps, bit-identical to the fused
+path), the 64 x 128 workload (plain and graph-replayed launches), copy probes of the attainable bandwidth, the batched ensemble
 (256 uneven FP32 lattices stepped by the autotuned engine, against the same
 lattices one at a time), and a bounded sample of the serving workload
 (Poisson arrivals of uneven FP64/FP32 requests stepped together by the
@@ -320,6 +321,7 @@ def main() -> int:
         print("--steps must be > 0 and --warmup >= 0", file=sys.stderr)
         return 2
 
+    import numpy as np
     import torch
     if not torch.cuda.is_available():
         print("no GPU visible: bench.py needs an MI355X", file=sys.stderr)
@@ -350,6 +352,32 @@ def main() -> int:
     if cons[4] != 0:
         log(f"non-finite populations after the run: {cons[4]}")
         return 1
+
+    # the two-step path (two steps per launch pair, bit-identical to the
+    # fused path): an even number of timed steps, so that every timed
+    # launch is a two-step pair; its moments after the same number of
+    # steps must equal the fused path's bit for bit
+    steps2 = max(2, args.steps - args.steps % 2)
+    log(f"two-step path {lx}x{ly}: {args.warmup} warmup + {steps2} timed steps")
+    r6 = time_path(lbm, ns, rt, lbm.LBM_PATH_FUSED2, steps2, args.warmup, extra, fields=True)
+    w6 = r6["wall"]
+    pair_ms = r6["span_ms"] / (steps2 // 2)
+    pair_bytes = 2 * 37 * 8 * sites  # each site read and written once per two steps
+    two_step = {"mlups": sites * steps2 / w6 / 1e6, "ms_per_step": w6 / steps2 * 1e3,
+                "steps": steps2, "speedup_vs_fused": (wall / args.steps) / (w6 / steps2),
+                "identical_to_fused": (steps2 == args.steps
+                                       and all(np.array_equal(a, b) for a, b in zip(fp64_fields, r6["moments"]))),
+                "launch_pair": {"launches": steps2 // 2, "avg_ms": pair_ms,
+                                "timing": "two HIP events bracketing the timed launches",
+                                "algorithmic_bytes": pair_bytes,
+                                "gbs": pair_bytes / (pair_ms * 1e-3) / 1e9,
+                                "hbm_frac": pair_bytes / (pair_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                "bytes_per_site_update": pair_bytes / (2 * sites)}}
+    del r6
+    log(f"two-step: {two_step['mlups']:.1f} MLUPS ({two_step['speedup_vs_fused']:.3f} x fused), "
+        f"{pair_ms:.3f} ms per launch pair = {two_step['launch_pair']['gbs']:.0f} GB/s of "
+        f"{two_step['launch_pair']['bytes_per_site_update']:.0f} B per site-update; identical to fused: "
+        f"{two_step['identical_to_fused']}")
 
     other_layout = None
     if not args.no_layout_compare:
@@ -456,7 +484,7 @@ def main() -> int:
                        "kind": args.layout, "nx": layout[0], "ny_pitch": layout[1],
                        "pstride": layout[2], "cstride": layout[3], "block": layout[5]}},
         "roofline": roofline, "cpu_baseline": cpu, "kernels": kern, "separate": separate,
-        "bandwidth_probe": copy, "reduced_storage": reduced, "regions": regions,
+        "bandwidth_probe": copy, "reduced_storage": reduced, "regions": regions, "two_step": two_step,
         "other_layout": other_layout, "batched_ensemble": ensemble, "ensemble_serving": serving,
         "small_lattice_64x128": small,
         "paper_equivalent_gflops": 6472 * sites * args.steps / wall / 1e9,

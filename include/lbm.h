@@ -82,12 +82,26 @@ typedef enum {
                             reference layer boundary lies inside the lattice
                             add a small launch over the (at most two)
                             wavefronts per column that straddle it */
-  LBM_PATH_REGIONS = 2   /* region split (Sec. 5, 1-D tiling): the fused
+  LBM_PATH_REGIONS = 2,  /* region split (Sec. 5, 1-D tiling): the fused
                             kernel on the bulk columns 3..Lx-4 runs on the
                             bound stream while a second stream refreshes
                             the halos (pbc) and steps the 3 + 3 border
                             columns, ordered by events across steps only;
                             same results as LBM_PATH_FUSED bit for bit */
+  LBM_PATH_FUSED2 = 3    /* two steps per launch (temporal blocking; the
+                            fusion of Sec. 5 carried across two steps):
+                            each wavefront marches along x over a strip of
+                            64 rows, steps each column once and the column
+                            three behind it a second time, keeping the
+                            intermediate populations in registers and LDS,
+                            so each site is read and written once per two
+                            steps.  LBM_FP64 storage only (EINVAL
+                            otherwise); same results as LBM_PATH_FUSED bit
+                            for bit.  Interior strips run on the bound
+                            stream, the strips holding wall rows on a
+                            second stream beside them.  An odd last step,
+                            and every step of a lattice lower than 64 rows,
+                            takes the fused kernel */
 } lbm_path;
 
 /* Population layout in each lattice copy.  Columns X = 0 .. Lx+5 include
@@ -117,7 +131,9 @@ typedef enum {
                               periodic x by wrapping (reads no halo) */
   LBM_PHASE_FUSED_BULK = 5,   /* timing only: region path, bulk columns */
   LBM_PHASE_FUSED_BORDER = 6, /* timing only: region path, border columns */
-  LBM_NPHASES = 7
+  LBM_PHASE_FUSED2 = 7,       /* timing only: two-step path, interior
+                                 strips (one launch per two steps) */
+  LBM_NPHASES = 8
 } lbm_phase;
 
 typedef struct {

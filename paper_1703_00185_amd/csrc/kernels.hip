@@ -428,6 +428,172 @@ __global__ void __launch_bounds__(BLOCK, BAND ? 1 : C::kMinWaves) fused_kernel(c
   fused_site<C, BLOCK, WRAP, BAND, RUN_OFF>(g, cd, src, dst, c, w, cols, x, y, ywave);
 }
 
+// ---------------------------------------------------------------------------
+// Two steps per launch (temporal blocking in registers), binary64 storage
+// ---------------------------------------------------------------------------
+// One wavefront takes a strip of 64 consecutive rows (row base + lane) and
+// marches along x over a segment of columns.  At column x1 it does the
+// first step of that column (the pull of Eq. (10), the walls, the
+// collision) and then the second step of column x1 - 3: the second pull
+// of population l reads the first step's output at column x1 - 3 - e_lx,
+// stepped 3 + e_lx columns ago, and at row y - e_ly, held by lane
+// lane - e_ly (a cross-lane permute).  Each population of the first step's
+// output stays in a per-population shift register exactly 3 + e_lx columns
+// (111 binary64 values per lane in all), so the intermediate lattice never
+// reaches memory: per site and two steps, 296 bytes are read and 296
+// written, instead of twice that.  The price is overlap: a strip's edge
+// lanes are not outputs unless they lie at a wall (their second pull would
+// need rows of the neighbouring strip), so a strip yields 58 rows (61 at a
+// wall), and a segment of n output columns steps n + 6 columns once.
+//
+// Strips: strip k has base = min(58 k, ly - 64) and outputs rows
+// [k == 0 ? 0 : 58 k + 3, k == last ? ly : 58 k + 61); ly >= 64.  Rows
+// beyond a wall are replaced as in gather_wall: in the first step from
+// the source lattice, in the second from the first step's output at the
+// site itself, population opp(l).  Where that population's shift register
+// no longer holds column x1 - 3 (e_x(opp(l)) < 0) it comes from a small
+// LDS stash that the wall lanes (lanes 0-2 and 61-63) fill, four columns
+// deep.
+//
+// Arithmetic is that of the fused kernel, operation for operation
+// (gather_interior / gather_wall, thermalise, collide_site), so two steps
+// of this kernel equal two launches of the fused kernel bit for bit.
+constexpr int STRIP_OUT = WAVE - 2 * HALO;  // 58 output rows per interior strip
+
+// Population l waits lag_of(l) = 3 + e_lx columns between its first and its
+// second step.  The short waits (at most 3 columns, 40 values) are shift
+// registers; the long ones (4-6 columns, 71 values) are circular buffers
+// in LDS, one 64-lane row of binary64 per slot and each lane touching only
+// its own column of it, so no barrier is needed.  Both together would not
+// fit the 512 registers of a lane without spilling.
+constexpr int lag_of(int l) { return HALO + EX[l]; }
+constexpr int LDS_LAG = 4;  // lags from 4 up live in LDS
+constexpr bool in_lds(int l) { return lag_of(l) >= LDS_LAG; }
+constexpr int ring_off(int l) {
+  int o = 0;
+  for (int k = 0; k < l; ++k) o += in_lds(k) ? 0 : lag_of(k);
+  return o;
+}
+constexpr int lds_off(int l) {
+  int o = 0;
+  for (int k = 0; k < l; ++k) o += in_lds(k) ? lag_of(k) : 0;
+  return o;
+}
+constexpr int RING_LEN = ring_off(NPOP);
+constexpr int LDS_SLOTS = lds_off(NPOP);
+static_assert(RING_LEN + LDS_SLOTS == 3 * NPOP, "the e_x of the velocity set sum to zero");
+constexpr int STASH_COLS = 4;   // columns x1 - 3 .. x1
+constexpr int STASH_LANES = 6;  // lanes 0-2 and 61-63
+
+__device__ __forceinline__ double lane_fetch(double v, int src_lane) {
+  const int addr = src_lane << 2;  // ds_bpermute takes lane * 4, modulo 64 lanes
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, static_cast<int>(b));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, static_cast<int>(b >> 32));
+  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+// Column position j mod L of the circular buffer of lag L (L = 4, 5, 6).
+__device__ __forceinline__ int lds_pos(int l, int r4, int r5, int r6) {
+  return lag_of(l) == 4 ? r4 : lag_of(l) == 5 ? r5 : r6;
+}
+
+template <bool WALL>
+__global__ void __launch_bounds__(WAVE, 1) fused2_kernel(const double* __restrict__ src, double* __restrict__ dst,
+                                                       Geometry g, CollideParams c, WallParams w,
+                                                       Fused2Strips st) {
+  __shared__ double lring[LDS_SLOTS][WAVE];
+  __shared__ double stash[WALL ? STASH_COLS : 1][WALL ? NPOP : 1][STASH_LANES];
+  const CodecF64 cd{};
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int i = tile % st.count;
+  const int seg = tile / st.count;
+  const int strip = WALL ? (i == 0 ? 0 : st.first + i - 1) : st.first + i;
+  const int lane = static_cast<int>(threadIdx.x);
+  const int base = min(strip * STRIP_OUT, g.ly - WAVE);
+  const int y = base + lane;
+  const int out_lo = strip == 0 ? 0 : strip * STRIP_OUT + HALO;
+  const int out_hi = strip == st.nstrip - 1 ? g.ly : strip * STRIP_OUT + STRIP_OUT + HALO;
+  const bool out = y >= out_lo && y < out_hi;
+  const bool wall_row = y < WALL_ROWS || y >= g.ly - WALL_ROWS;
+  const int slot = lane < WALL_ROWS ? lane : lane - (WAVE - 2 * WALL_ROWS);
+  const int x_first = seg * st.seg_w;
+  const int nout = min(st.seg_w, g.lx - x_first);
+  int x1 = x_first - HALO;
+  if (x1 < 0) x1 += g.lx;
+  double ring[RING_LEN];
+#pragma unroll
+  for (int r = 0; r < RING_LEN; ++r) ring[r] = 0.0;
+  int r4 = 0, r5 = 0, r6 = 0;  // j mod 4, 5, 6
+  // the loads of each column are issued one column ahead (a lone
+  // wavefront per SIMD hides no memory latency by switching)
+  auto gather = [&](int x, double(&v)[NPOP]) {
+    if constexpr (WALL) gather_wall<true>(g, cd, src, x, y, v);
+    else gather_interior<true>(g, cd, src, x, y, v);
+  };
+  double next[NPOP];
+  gather(x1, next);
+  const int ncol = nout + 2 * HALO;
+  for (int j = 0; j < ncol; ++j) {
+    double f[NPOP];
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) f[l] = next[l];
+    if (j + 1 < ncol) gather(x1 + 1 == g.lx ? 0 : x1 + 1, next);
+    if (WALL && wall_row) thermalise(f, y < WALL_ROWS, w);
+    collide_site(f, c);
+    // the wall lanes keep the whole site four columns deep: the second
+    // step's bounce-back at column x1 - 3 reads it
+    if (WALL && wall_row) {
+#pragma unroll
+      for (int k = 0; k < NPOP; ++k) stash[j % STASH_COLS][k][slot] = f[k];
+    }
+    // advance every buffer by column x1, taking out what the second step
+    // of column x1 - 3 pulls (one population at a time, so that f and q
+    // together hold one site)
+    double q[NPOP];
+#pragma unroll
+    for (int l = 0; l < NPOP; ++l) {
+      if (lag_of(l) == 0) {
+        q[l] = f[l];
+      } else if (in_lds(l)) {
+        double* cell = &lring[lds_off(l) + lds_pos(l, r4, r5, r6)][lane];
+        q[l] = *cell;
+        *cell = f[l];
+      } else {
+        q[l] = ring[ring_off(l)];
+#pragma unroll
+        for (int r = 0; r + 1 < lag_of(l); ++r) ring[ring_off(l) + r] = ring[ring_off(l) + r + 1];
+        ring[ring_off(l) + lag_of(l) - 1] = f[l];
+      }
+    }
+    const bool second = j >= 2 * HALO;
+    if (second) {
+#pragma unroll
+      for (int l = 0; l < NPOP; ++l)
+        if (EY[l] != 0) q[l] = lane_fetch(q[l], lane - EY[l]);
+      if (WALL && wall_row) {
+#pragma unroll
+        for (int l = 0; l < NPOP; ++l) {
+          if (EY[l] == 0) continue;
+          const int ys = y - EY[l];
+          if (ys < 0 || ys >= g.ly) q[l] = stash[(j + 1) % STASH_COLS][opp_of(l)][slot];
+        }
+      }
+    }
+    r4 = r4 == 3 ? 0 : r4 + 1;
+    r5 = r5 == 4 ? 0 : r5 + 1;
+    r6 = r6 == 5 ? 0 : r6 + 1;
+    if (second) {
+      if (WALL && wall_row) thermalise(q, y < WALL_ROWS, w);
+      collide_site(q, c);
+      int x2 = x1 - HALO;
+      if (x2 < 0) x2 += g.lx;
+      if (out) store_column_site(g, cd, dst, x2, y, q);
+    }
+    x1 = x1 + 1 == g.lx ? 0 : x1 + 1;
+  }
+}
+
 // Per-site rho, ux, uy, T into out[4][lx][ly] (Sec. 2 moment definitions;
 // D rho T = sum |c|^2 f - rho |u|^2).
 template <class C>
@@ -731,6 +897,66 @@ hipError_t launch_fused(const Geometry& g, const void* src, void* dst, const Col
   band.y0 = first;
   band.nyb = (last + WAVE - first + g.block - 1) / g.block;
   return launch_fused_rows(g, src, dst, c, w, s, band, ncols, band.nyb, wrap);
+}
+
+constexpr int kMinSegment = 16;
+
+Fused2Plan fused2_plan(const Geometry& g, int simds) {
+  Fused2Plan p{};
+  if (g.storage != STORAGE_F64 || g.ly < WAVE || simds < 1) return p;
+  const int nstrip = (g.ly - WAVE + STRIP_OUT - 1) / STRIP_OUT + 1;
+  // strips 1 .. n_int whose 64 rows hold no wall row (base + 64 <= ly - 3);
+  // the others (strip 0, the last ones) take the wall kernel
+  int last_int = g.ly >= WAVE + WALL_ROWS + STRIP_OUT ? (g.ly - WALL_ROWS - WAVE) / STRIP_OUT : 0;
+  last_int = std::min(last_int, nstrip - 2);
+  const int n_int = std::max(last_int, 0);
+  // Segments per strip: one wavefront per SIMD is resident (the kernel
+  // holds more than 256 registers), and a wavefront's time is the columns
+  // it steps, segment + 6.  Measured on 2048 x 8192: one round of
+  // wavefronts (7 segments of 293 columns) ran 9 % faster than any shape
+  // of several rounds, whatever their segment width.  The wall strips run
+  // beside the interior ones, each wall column costing about 1.7 interior
+  // ones (the wall gather and bounce-back), so their segments are a third
+  // as wide: they finish within the interior wavefronts' time and fill
+  // the SIMDs the interior round leaves.  So minimise rounds x (segment +
+  // 6) over both launches, several rounds weighted by 1.1.
+  const int n_wall = nstrip - n_int;
+  auto wall_width = [&](int sw) { return std::min(g.lx, std::max(kMinSegment / 2, (sw + 2) / 3)); };
+  int best_n = 1;
+  double best = -1.0;
+  for (int nseg = 1; nseg <= g.lx; ++nseg) {
+    const int sw = (g.lx + nseg - 1) / nseg;
+    if (nseg > 1 && (g.lx + nseg - 2) / (nseg - 1) == sw) continue;  // same width as nseg - 1
+    if (nseg > 1 && sw < kMinSegment) break;  // 6 extra columns per few outputs
+    const int ww = wall_width(sw);
+    const long long waves =
+        static_cast<long long>(n_int) * nseg + static_cast<long long>(n_wall) * ((g.lx + ww - 1) / ww);
+    const long long rounds = (waves + simds - 1) / simds;
+    const double cost = static_cast<double>(rounds) * (sw + 2 * HALO) * (rounds > 1 ? 1.1 : 1.0);
+    if (best < 0.0 || cost < best) best = cost, best_n = nseg;
+  }
+  const int seg_w = (g.lx + best_n - 1) / best_n;
+  p.interior = Fused2Strips{1, n_int, nstrip, seg_w};
+  p.wall = Fused2Strips{1 + n_int, n_wall, nstrip, wall_width(seg_w)};
+  p.ok = 1;
+  return p;
+}
+
+hipError_t launch_fused2(const Geometry& g, const void* src, void* dst, const CollideParams& c,
+                         const WallParams& w, const Fused2Strips& st, bool wall, hipStream_t s) {
+  if (!(g.storage == STORAGE_F64 && g.ly >= WAVE && st.seg_w >= 1 && st.count >= 0 && st.nstrip >= 1))
+    return hipErrorInvalidValue;
+  if (st.count == 0) return hipSuccess;
+  const long long grid = static_cast<long long>(st.count) * ((g.lx + st.seg_w - 1) / st.seg_w);
+  if (grid >= (1LL << 31)) return hipErrorInvalidValue;
+  (void)hipGetLastError();
+  if (wall)
+    hipLaunchKernelGGL(fused2_kernel<true>, dim3(static_cast<unsigned>(grid)), dim3(WAVE), 0, s,
+                       static_cast<const double*>(src), static_cast<double*>(dst), g, c, w, st);
+  else
+    hipLaunchKernelGGL(fused2_kernel<false>, dim3(static_cast<unsigned>(grid)), dim3(WAVE), 0, s,
+                       static_cast<const double*>(src), static_cast<double*>(dst), g, c, w, st);
+  return hipGetLastError();
 }
 
 hipError_t launch_fused_rows(const Geometry& g, const void* src, void* dst, const CollideParams& c,

@@ -114,6 +114,25 @@ hipError_t launch_fused(const Geometry& g, const void* src, void* dst, const Col
 hipError_t launch_fused_rows(const Geometry& g, const void* src, void* dst, const CollideParams& c,
                              const WallParams& w, hipStream_t s, const ColumnSet& cs, int ncols, int nyb,
                              bool wrap);
+// Two steps per launch (binary64 storage, ly >= 64, periodic x by
+// wrapping): src -> dst equals two launch_fused steps through an
+// intermediate lattice that is never stored.  The rows are cut into strips
+// of 64 (58 output rows each, strip k from row 58 k); the interior strips
+// and the strips holding wall rows take two kernels, which write disjoint
+// rows and may run concurrently.  Strips of a launch: `count` strips from
+// `first` (the wall launch: strip 0, then count - 1 strips from first),
+// `nstrip` strips in all, `seg_w` output columns per wavefront.
+struct Fused2Strips {
+  int first, count, nstrip, seg_w;
+};
+struct Fused2Plan {
+  int ok;  // 0: the lattice does not qualify (storage or ly < 64)
+  Fused2Strips interior, wall;
+};
+// simds: SIMDs of the device (4 per compute unit).
+Fused2Plan fused2_plan(const Geometry& g, int simds);
+hipError_t launch_fused2(const Geometry& g, const void* src, void* dst, const CollideParams& c,
+                         const WallParams& w, const Fused2Strips& st, bool wall, hipStream_t s);
 hipError_t launch_moments(const Geometry& g, const void* f, double* out, hipStream_t s);
 hipError_t launch_conservation(const Geometry& g, const void* f, double* partials, double* result,
                                hipStream_t s);

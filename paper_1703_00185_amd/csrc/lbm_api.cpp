@@ -60,8 +60,12 @@ int make_layout(const lbm_config* c, Layout* out, std::string* why) {
     return *why = "storage must be LBM_FP64, LBM_FP32 or LBM_FP16DEV", LBM_EINVAL;
   if (c->layout != LBM_LAYOUT_COLUMN && c->layout != LBM_LAYOUT_PLANAR)
     return *why = "layout must be LBM_LAYOUT_COLUMN or LBM_LAYOUT_PLANAR", LBM_EINVAL;
-  if (c->path != LBM_PATH_SEPARATE && c->path != LBM_PATH_FUSED && c->path != LBM_PATH_REGIONS)
-    return *why = "path must be LBM_PATH_SEPARATE, LBM_PATH_FUSED or LBM_PATH_REGIONS", LBM_EINVAL;
+  if (c->path != LBM_PATH_SEPARATE && c->path != LBM_PATH_FUSED && c->path != LBM_PATH_REGIONS &&
+      c->path != LBM_PATH_FUSED2)
+    return *why = "path must be LBM_PATH_SEPARATE, LBM_PATH_FUSED, LBM_PATH_REGIONS or LBM_PATH_FUSED2",
+           LBM_EINVAL;
+  if (c->path == LBM_PATH_FUSED2 && c->storage != LBM_FP64)
+    return *why = "LBM_PATH_FUSED2 takes LBM_FP64 storage (its intermediate step is binary64)", LBM_EINVAL;
   const int block = c->block == 0 ? default_block(c->storage, c->lx, c->ly) : c->block;
   if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
     return *why = "block must be 0, 64, 128, 256, 512 or 1024", LBM_EINVAL;
@@ -205,6 +209,42 @@ int region_steps(lbm_handle* h, int32_t n) {
     h->cur ^= 1;
   }
   LBM_HIP(h, hipStreamWaitEvent(h->stream, h->ev_border, 0));
+  return LBM_OK;
+}
+
+// n steps of the two-step path: n / 2 launch pairs, then one fused step
+// if n is odd.  A pair steps the interior strips on the caller's stream
+// and the wall strips on the side stream concurrently (they write disjoint
+// rows of the destination and read only the source); the side stream
+// waits for everything before the pair and the caller's stream for the
+// wall launch after it, so each pair is ordered on the caller's stream as
+// a whole.  Lattices lower than 64 rows take fused steps.
+int fused2_steps(lbm_handle* h, int32_t n) {
+  const Geometry& g = h->geo;
+  int cus = 0;
+  LBM_HIP(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
+  const Fused2Plan plan = fused2_plan(g, 4 * cus);
+  int rc = LBM_OK;
+  if (plan.ok && n >= 2) {
+    rc = ensure_side(h);
+    if (rc != LBM_OK) return rc;
+    for (; n >= 2; n -= 2) {
+      LBM_HIP(h, hipEventRecord(h->ev_ready, h->stream));
+      LBM_HIP(h, hipStreamWaitEvent(h->side, h->ev_ready, 0));
+      LBM_HIP(h, launch_fused2(g, current(h), other(h), h->cp, h->wp, plan.wall, true, h->side));
+      LBM_HIP(h, hipEventRecord(h->ev_border, h->side));
+      rc = timed(h, LBM_PHASE_FUSED2, [&] {
+        return launch_fused2(g, current(h), other(h), h->cp, h->wp, plan.interior, false, h->stream);
+      });
+      if (rc != LBM_OK) return rc;
+      LBM_HIP(h, hipStreamWaitEvent(h->stream, h->ev_border, 0));
+      h->cur ^= 1;
+    }
+  }
+  for (; n > 0; --n) {
+    rc = fused_step(h);
+    if (rc != LBM_OK) return rc;
+  }
   return LBM_OK;
 }
 
@@ -425,6 +465,7 @@ int lbm_step(lbm_handle* h, int32_t n) {
   if (h->engine) return fail(h, LBM_ESTATE, "lattice is stepped by an engine (remove it first)");
   DeviceGuard dg(h->device);
   if (h->cfg.path == LBM_PATH_REGIONS) return region_steps(h, n);
+  if (h->cfg.path == LBM_PATH_FUSED2) return fused2_steps(h, n);
   for (int32_t i = 0; i < n; ++i) {
     int rc;
     if (h->cfg.path == LBM_PATH_FUSED) {
@@ -457,7 +498,7 @@ int lbm_step_captured(lbm_handle* h, int32_t n) {
       cur_after = c.cur_after;
     }
   if (!exec) {
-    if (h->cfg.path == LBM_PATH_REGIONS) {
+    if (h->cfg.path == LBM_PATH_REGIONS || h->cfg.path == LBM_PATH_FUSED2) {
       // create the side stream outside the capture
       const int rs = ensure_side(h);
       if (rs != LBM_OK) return rs;

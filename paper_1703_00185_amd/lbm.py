@@ -21,12 +21,12 @@ NPOP = 37
 MAX_MODES = 32
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ESTATE = 0, -1, -2, -3, -4
 LBM_FP64, LBM_FP32, LBM_FP16DEV = 0, 1, 2
-LBM_PATH_SEPARATE, LBM_PATH_FUSED, LBM_PATH_REGIONS = 0, 1, 2
+LBM_PATH_SEPARATE, LBM_PATH_FUSED, LBM_PATH_REGIONS, LBM_PATH_FUSED2 = 0, 1, 2, 3
 LBM_LAYOUT_COLUMN, LBM_LAYOUT_PLANAR = 0, 1
 (LBM_PHASE_PBC, LBM_PHASE_PROPAGATE, LBM_PHASE_BC, LBM_PHASE_COLLIDE,
- LBM_PHASE_FUSED, LBM_PHASE_FUSED_BULK, LBM_PHASE_FUSED_BORDER) = range(7)
-LBM_NPHASES = 7
-PHASE_NAMES = ("pbc", "propagate", "bc", "collide", "fused", "fused_bulk", "fused_border")
+ LBM_PHASE_FUSED, LBM_PHASE_FUSED_BULK, LBM_PHASE_FUSED_BORDER, LBM_PHASE_FUSED2) = range(8)
+LBM_NPHASES = 8
+PHASE_NAMES = ("pbc", "propagate", "bc", "collide", "fused", "fused_bulk", "fused_border", "fused2")
 STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE", -4: "LBM_ESTATE"}
 
 

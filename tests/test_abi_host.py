@@ -69,7 +69,7 @@ def test_config_from_rejects_unknown_fields():
 @pytest.mark.parametrize("field,value,needle", [
     ("lx", 2, "lx"), ("ly", 5, "ly"), ("tau", 0.5, "tau"), ("tau", float("nan"), "tau"),
     ("t_bottom", 0.0, "temperature"), ("t_top", -1.0, "temperature"),
-    ("gy", float("inf"), "gravity"), ("storage", 7, "storage"), ("path", 3, "path"),
+    ("gy", float("inf"), "gravity"), ("storage", 7, "storage"), ("path", 4, "path"),
     ("block", 96, "block"), ("layout", 2, "layout"), ("layout", -1, "layout"),
 ])
 def test_invalid_config_rejected(field, value, needle):
@@ -82,6 +82,17 @@ def test_invalid_config_rejected(field, value, needle):
     with pytest.raises(lbm.LbmError) as ei:
         lbm.lbm_create(cfg, 1 << 20, 1 << 40, 0)
     assert ei.value.status == lbm.LBM_EINVAL
+
+
+@pytest.mark.parametrize("storage", [lbm.LBM_FP32, lbm.LBM_FP16DEV])
+def test_two_step_path_takes_binary64_storage_only(storage):
+    cfg = lbm.lbm_config_default(64, 128)
+    cfg.path = lbm.LBM_PATH_FUSED2
+    assert lbm.lbm_required_bytes(cfg) > 0
+    cfg.storage = storage
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.lbm_required_bytes(cfg)
+    assert ei.value.status == lbm.LBM_EINVAL and "LBM_PATH_FUSED2" in str(ei.value)
 
 
 def test_lattice_too_large_rejected():

@@ -180,4 +180,4 @@ def test_fp16dev_fused_step_is_one_wrapping_kernel():
         lat.step(3)
         ms, cnt = lbm.lbm_read_timing(lat.h)
         lbm.lbm_set_timing(lat.h, False)
-    assert cnt.tolist() == [0, 0, 0, 0, 3, 0, 0]
+    assert cnt.tolist() == [0, 0, 0, 0, 3, 0, 0, 0]

@@ -322,14 +322,14 @@ def test_timing_counters_and_state_errors():
         ms, cnt = lbm.lbm_read_timing(lat.h)
         lbm.lbm_set_timing(lat.h, False)
     # the fused path is one launch per step (periodic x by wrapping, no pbc)
-    assert cnt.tolist() == [0, 0, 0, 0, 3, 0, 0]
+    assert cnt.tolist() == [0, 0, 0, 0, 3, 0, 0, 0]
     assert ms[4] > 0
     with lattice(ns, path=lbm.LBM_PATH_SEPARATE) as lat:
         lat.init_rt(inputs.rt_perturbation(0, 128))
         lbm.lbm_set_timing(lat.h, True)
         lat.step(2)
         ms, cnt = lbm.lbm_read_timing(lat.h)
-    assert cnt.tolist() == [2, 2, 2, 2, 0, 0, 0]
+    assert cnt.tolist() == [2, 2, 2, 2, 0, 0, 0, 0]
     assert all(ms[p] > 0 for p in range(4))
 
 
