@@ -112,3 +112,26 @@ def test_two_step_captured_equals_plain():
             b.step_captured(n)
             assert np.array_equal(a.get(), b.get()), n
             b.conservation()
+
+
+def test_two_step_on_a_user_stream():
+    """Bound to a stream of the caller's (not the null stream): the wall
+    launch on the library's second stream is still ordered inside each
+    step call, so reading back right after equals the fused path."""
+    import torch
+    ns = inputs.rt_config(200, 190)
+    rt = inputs.rt_perturbation(9, 190)
+    with lattice(ns) as ref:
+        ref.init_rt(rt)
+        ref.step(6)
+        want = ref.get()
+    side = torch.cuda.Stream()
+    lat = lbm.Lattice(lbm.config_from(ns, path=lbm.LBM_PATH_FUSED2), stream=side)
+    try:
+        lat.init_rt(rt)
+        lat.step(2)
+        lat.step(4)
+        got = lat.get()
+    finally:
+        lat.close()
+    assert np.array_equal(got, want)
