@@ -429,7 +429,7 @@ __global__ void __launch_bounds__(BLOCK, BAND ? 1 : C::kMinWaves) fused_kernel(c
 }
 
 // ---------------------------------------------------------------------------
-// Two steps per launch (temporal blocking in registers), binary64 storage
+// Two steps per launch (temporal blocking on chip), binary64 storage
 // ---------------------------------------------------------------------------
 // One wavefront takes a strip of 64 consecutive rows (row base + lane) and
 // marches along x over a segment of columns.  At column x1 it does the
@@ -438,8 +438,8 @@ __global__ void __launch_bounds__(BLOCK, BAND ? 1 : C::kMinWaves) fused_kernel(c
 // of population l reads the first step's output at column x1 - 3 - e_lx,
 // stepped 3 + e_lx columns ago, and at row y - e_ly, held by lane
 // lane - e_ly (a cross-lane permute).  Each population of the first step's
-// output stays in a per-population shift register exactly 3 + e_lx columns
-// (111 binary64 values per lane in all), so the intermediate lattice never
+// output is kept exactly 3 + e_lx columns (111 binary64 values per lane in
+// all, in registers and LDS, below), so the intermediate lattice never
 // reaches memory: per site and two steps, 296 bytes are read and 296
 // written, instead of twice that.  The price is overlap: a strip's edge
 // lanes are not outputs unless they lie at a wall (their second pull would
@@ -450,10 +450,8 @@ __global__ void __launch_bounds__(BLOCK, BAND ? 1 : C::kMinWaves) fused_kernel(c
 // [k == 0 ? 0 : 58 k + 3, k == last ? ly : 58 k + 61); ly >= 64.  Rows
 // beyond a wall are replaced as in gather_wall: in the first step from
 // the source lattice, in the second from the first step's output at the
-// site itself, population opp(l).  Where that population's shift register
-// no longer holds column x1 - 3 (e_x(opp(l)) < 0) it comes from a small
-// LDS stash that the wall lanes (lanes 0-2 and 61-63) fill, four columns
-// deep.
+// site itself, population opp(l), which the wall lanes (lanes 0-2 and
+// 61-63) keep in a small LDS stash, the whole site four columns deep.
 //
 // The second step of a column is collided one iteration later, in the same
 // block as the next column's first step: the two collisions are
