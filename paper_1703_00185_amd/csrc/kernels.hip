@@ -17,6 +17,7 @@
 #pragma clang fp contract(off)
 
 #include "d2q37_device.hpp"
+#include "fused2_plan.hpp"
 #include "kernels.hpp"
 
 namespace d2q37 {
@@ -461,7 +462,7 @@ __global__ void __launch_bounds__(BLOCK, BAND ? 1 : C::kMinWaves) fused_kernel(c
 // Arithmetic is that of the fused kernel, operation for operation
 // (gather_interior / gather_wall, thermalise, collide_site), so two steps
 // of this kernel equal two launches of the fused kernel bit for bit.
-constexpr int STRIP_OUT = WAVE - 2 * HALO;  // 58 output rows per interior strip
+static_assert(F2_ROWS == WAVE, "a strip is one wavefront");
 
 // Population l waits lag_of(l) = 3 + e_lx columns between its first and its
 // second step.  The short waits (at most 3 columns, 40 values) are shift
@@ -511,13 +512,11 @@ __global__ void __launch_bounds__(WAVE, 1) fused2_kernel(const double* __restric
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int i = tile % st.count;
   const int seg = tile / st.count;
-  const int strip = WALL ? (i == 0 ? 0 : st.first + i - 1) : st.first + i;
+  const int strip = fused2_strip_of(st, WALL, i);
   const int lane = static_cast<int>(threadIdx.x);
-  const int base = min(strip * STRIP_OUT, g.ly - WAVE);
-  const int y = base + lane;
-  const int out_lo = strip == 0 ? 0 : strip * STRIP_OUT + HALO;
-  const int out_hi = strip == st.nstrip - 1 ? g.ly : strip * STRIP_OUT + STRIP_OUT + HALO;
-  const bool out = y >= out_lo && y < out_hi;
+  const Fused2Rows rows = fused2_rows(strip, st.nstrip, g.ly);
+  const int y = rows.base + lane;
+  const bool out = y >= rows.out_lo && y < rows.out_hi;
   const bool wall_row = y < WALL_ROWS || y >= g.ly - WALL_ROWS;
   const int slot = lane < WALL_ROWS ? lane : lane - (WAVE - 2 * WALL_ROWS);
   const int x_first = seg * st.seg_w;
@@ -899,52 +898,10 @@ hipError_t launch_fused(const Geometry& g, const void* src, void* dst, const Col
   return launch_fused_rows(g, src, dst, c, w, s, band, ncols, band.nyb, wrap);
 }
 
-constexpr int kMinSegment = 16;
-
-Fused2Plan fused2_plan(const Geometry& g, int simds) {
-  Fused2Plan p{};
-  if (g.storage != STORAGE_F64 || g.ly < WAVE || simds < 1) return p;
-  const int nstrip = (g.ly - WAVE + STRIP_OUT - 1) / STRIP_OUT + 1;
-  // strips 1 .. n_int whose 64 rows hold no wall row (base + 64 <= ly - 3);
-  // the others (strip 0, the last ones) take the wall kernel
-  int last_int = g.ly >= WAVE + WALL_ROWS + STRIP_OUT ? (g.ly - WALL_ROWS - WAVE) / STRIP_OUT : 0;
-  last_int = std::min(last_int, nstrip - 2);
-  const int n_int = std::max(last_int, 0);
-  // Segments per strip: one wavefront per SIMD is resident (the kernel
-  // holds more than 256 registers), and a wavefront's time is the columns
-  // it steps, segment + 6.  Measured on 2048 x 8192: one round of
-  // wavefronts (7 segments of 293 columns) ran 9 % faster than any shape
-  // of several rounds, whatever their segment width.  The wall strips run
-  // beside the interior ones, each wall column costing about 1.7 interior
-  // ones (the wall gather and bounce-back), so their segments are a third
-  // as wide: they finish within the interior wavefronts' time and fill
-  // the SIMDs the interior round leaves.  So minimise rounds x (segment +
-  // 6) over both launches, several rounds weighted by 1.1.
-  const int n_wall = nstrip - n_int;
-  auto wall_width = [&](int sw) { return std::min(g.lx, std::max(kMinSegment / 2, (sw + 2) / 3)); };
-  int best_n = 1;
-  double best = -1.0;
-  for (int nseg = 1; nseg <= g.lx; ++nseg) {
-    const int sw = (g.lx + nseg - 1) / nseg;
-    if (nseg > 1 && (g.lx + nseg - 2) / (nseg - 1) == sw) continue;  // same width as nseg - 1
-    if (nseg > 1 && sw < kMinSegment) break;  // 6 extra columns per few outputs
-    const int ww = wall_width(sw);
-    const long long waves =
-        static_cast<long long>(n_int) * nseg + static_cast<long long>(n_wall) * ((g.lx + ww - 1) / ww);
-    const long long rounds = (waves + simds - 1) / simds;
-    const double cost = static_cast<double>(rounds) * (sw + 2 * HALO) * (rounds > 1 ? 1.1 : 1.0);
-    if (best < 0.0 || cost < best) best = cost, best_n = nseg;
-  }
-  const int seg_w = (g.lx + best_n - 1) / best_n;
-  p.interior = Fused2Strips{1, n_int, nstrip, seg_w};
-  p.wall = Fused2Strips{1 + n_int, n_wall, nstrip, wall_width(seg_w)};
-  p.ok = 1;
-  return p;
-}
-
 hipError_t launch_fused2(const Geometry& g, const void* src, void* dst, const CollideParams& c,
                          const WallParams& w, const Fused2Strips& st, bool wall, hipStream_t s) {
-  if (!(g.storage == STORAGE_F64 && g.ly >= WAVE && st.seg_w >= 1 && st.count >= 0 && st.nstrip >= 1))
+  if (!(g.storage == STORAGE_F64 && g.ly >= F2_ROWS && st.seg_w >= 1 && st.count >= 0 &&
+        st.nstrip == fused2_strips(g.ly)))
     return hipErrorInvalidValue;
   if (st.count == 0) return hipSuccess;
   const long long grid = static_cast<long long>(st.count) * ((g.lx + st.seg_w - 1) / st.seg_w);

@@ -129,8 +129,7 @@ struct Fused2Plan {
   int ok;  // 0: the lattice does not qualify (storage or ly < 64)
   Fused2Strips interior, wall;
 };
-// simds: SIMDs of the device (4 per compute unit).
-Fused2Plan fused2_plan(const Geometry& g, int simds);
+// fused2_plan (fused2_plan.hpp) picks the strips and segments of a lattice.
 hipError_t launch_fused2(const Geometry& g, const void* src, void* dst, const CollideParams& c,
                          const WallParams& w, const Fused2Strips& st, bool wall, hipStream_t s);
 hipError_t launch_moments(const Geometry& g, const void* f, double* out, hipStream_t s);

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "fused2_plan.hpp"
 #include "kernels.hpp"
 #include "lbm.h"
 

@@ -144,13 +144,6 @@ hipError_t launch_fused(const Geometry& g, const void* src, void* dst, const Col
                         hipStream_t s, const ColumnSet*, bool) {
   return launch_propagate(g, src, dst, s);
 }
-Fused2Plan fused2_plan(const Geometry& g, int) {
-  Fused2Plan p{};
-  p.ok = g.storage == STORAGE_F64 && g.ly >= 64;
-  p.interior = Fused2Strips{1, 1, 3, g.lx};
-  p.wall = Fused2Strips{2, 2, 3, g.lx};
-  return p;
-}
 hipError_t launch_fused2(const Geometry& g, const void* src, void* dst, const CollideParams&, const WallParams&,
                          const Fused2Strips&, bool, hipStream_t s) {
   return launch_propagate(g, src, dst, s);
